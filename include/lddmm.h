@@ -1,0 +1,181 @@
+/*
+ * lddmm.h -- C ABI of the masked-LDDMM registration library for AMD MI355X (gfx950).
+ *
+ * Method: Kutten et al., "Deformably Registering and Annotating Whole CLARITY
+ * Brains to an Atlas via Masked LDDMM", Proc. SPIE 9896 (2016).
+ *
+ *   Methods, Registration: minimise by gradient descent
+ *       E(v) = int_0^1 ||L v_t||^2 dt + sigma^-2 ||J0 o phi_10 - J1||^2,
+ *       L = (-alpha Lap + gamma) I_3 ;  gamma = sigma = 1 by convention ;
+ *       v discretised in time; phi_10 pulls the template into target space.
+ *   Methods, Preprocessing: Mask-LDDMM replaces I0, I1 by the masks M0, M1
+ *       (channel weights {1, 0}); the masked images M*I form the second channel.
+ *   Methods, Postprocessing: labels are deformed with nearest-neighbour
+ *       interpolation (L0 o phi^-1).
+ *
+ * Conventions shared by every call
+ *   - All array pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
+ *     owned by the caller.  The library never allocates or frees device memory;
+ *     scratch comes from the caller's workspace.
+ *   - Scalar fields are contiguous FP32, index = (z*ny + y)*nx + x (x fastest).
+ *     Vector fields are 3 consecutive planes (x, y, z components).  The velocity
+ *     is [T][3][P] where P is the computational grid of the finest level
+ *     (lddmm_comp_grid): each axis of the user grid N padded at the high end to a
+ *     7-smooth length (and, with several levels, nested: P = 2^(L-1) * P_coarsest).
+ *   - Displacements u = phi - id are in the physical units of `spacing`.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *     marked async only enqueue work; lddmm_register synchronises once at exit.
+ *   - Errors: arguments are checked on the host before any launch; a bad
+ *     argument returns LDDMM_EINVAL and enqueues nothing.  A HIP launch/runtime
+ *     error returns LDDMM_EHIP.  Numeric trouble in the async calls shows up as
+ *     NaN in their FP64 outputs.
+ *   - Calls are reentrant across distinct workspaces; two calls that share a
+ *     workspace must be ordered on one stream.
+ */
+#ifndef LDDMM_H
+#define LDDMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LDDMM_OK          0
+#define LDDMM_EINVAL     -1   /* null pointer, size < 2 or > LDDMM_MAX_DIM, T < 1,
+                                 alpha/gamma/sigma/spacing <= 0, workspace too small */
+#define LDDMM_EHIP       -2   /* HIP runtime or launch error */
+#define LDDMM_ENONFINITE -3   /* energy not finite (NaN/Inf velocity or inputs) */
+#define LDDMM_WFOLD       1   /* warning: min det D(phi_{t,1}) <= 0 seen; result written */
+#define LDDMM_WGUARD      2   /* warning: a level stopped after LDDMM_MAX_HALVINGS step halvings */
+
+#define LDDMM_GRAD_V      0   /* Beg's gradient in V: g_j = 2 v_j - K b_j */
+#define LDDMM_GRAD_L2     1   /* exact gradient dE/dv of the discrete energy */
+
+#define LDDMM_INTERP_LINEAR  0
+#define LDDMM_INTERP_NEAREST 1
+#define LDDMM_F32 0
+#define LDDMM_I32 1
+
+#define LDDMM_MAX_LEVELS    4
+#define LDDMM_MAX_DIM       1024
+#define LDDMM_MAX_T         64
+#define LDDMM_MAX_HALVINGS  10
+#define LDDMM_TRACE_COLS    8   /* E, R, D, step, min det, image SSD, accepted, E_best */
+
+/* flags */
+#define LDDMM_FLAG_RECOMPUTE_PHI 1   /* exact gradient: recompute phi_t from checkpoints */
+
+/* User grid N (voxels) and the voxel spacing h of the finest level. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double spacing;
+} lddmm_grid;
+
+/* Constants of the objective (Methods, Registration) and of the descent. */
+typedef struct {
+  double alpha, gamma, sigma;        /* L = (-alpha Lap + gamma) I3 ; data weight 1/sigma^2 */
+  int32_t n_timesteps;               /* T: v is piecewise constant on T intervals */
+  int32_t n_levels;                  /* pyramid levels, each halving the resolution */
+  int32_t iters[LDDMM_MAX_LEVELS];   /* iteration slots per level, coarsest first */
+  double step;                       /* gradient step epsilon (reset at each level) */
+  int32_t guard;                     /* 1: reject energy increases and halve the step */
+  double weight[2];                  /* channel weights {mask, masked image}; {1,0} = Mask-LDDMM */
+  int32_t flags;                     /* LDDMM_FLAG_* */
+  int32_t checkpoint_every;          /* exact gradient with RECOMPUTE_PHI: checkpoint spacing */
+} lddmm_params;
+
+/* One registration problem.  Images are on the user grid N. */
+typedef struct {
+  lddmm_grid grid;
+  const float *template_mask;        /* M0 [N] */
+  const float *template_image;       /* M0*I0 [N] or NULL */
+  const float *target_mask;          /* M1 [N] */
+  const float *target_image;         /* M1*I1 [N] or NULL (NULL iff template_image is NULL) */
+  float *v;                          /* [T][3][P_finest]: in = initial velocity, out = result */
+  float *phi10;                      /* out: u0_T = phi_10 - id on N, [3][N]; may be NULL */
+  float *phi01;                      /* out: u1_0 = phi_01 - id on N, [3][N]; may be NULL */
+  double *trace;                     /* out: per level (iters+1) rows x LDDMM_TRACE_COLS; may be NULL */
+  void *workspace;                   /* caller-allocated device scratch */
+  size_t workspace_bytes;            /* >= lddmm_workspace_size(&grid, params) */
+} lddmm_problem;
+
+/* Bytes of device workspace one problem needs (0 if the arguments are invalid). */
+size_t lddmm_workspace_size(const lddmm_grid *grid, const lddmm_params *params);
+
+/* Computational grid of pyramid level `level` (0 = finest): out_P = {nx, ny, nz}.
+   Returns LDDMM_OK or LDDMM_EINVAL. */
+int lddmm_comp_grid(const lddmm_grid *grid, const lddmm_params *params, int32_t level,
+                    int32_t out_P[3]);
+
+/* Number of trace rows a registration writes: sum over levels of (iters + 1). */
+int32_t lddmm_trace_rows(const lddmm_params *params);
+
+/*
+ * Register: coarse-to-fine gradient descent on E(v) (Methods, Registration).
+ * Per level: images and v_init are block-averaged from the finest grid; each
+ * iteration slot either takes a gradient step v - eps*g (g = 2v - K b, Beg's
+ * V-gradient) or, after a rejected trial, halves eps and retries the midpoint;
+ * with guard=1 a trial is accepted iff its energy does not exceed the current
+ * one.  v is upsampled (cell-centred trilinear) between levels.  The guard is
+ * decided on the device; the call synchronises `stream` once at exit and
+ * returns LDDMM_OK, a warning (LDDMM_WFOLD / LDDMM_WGUARD) or an error.
+ * n_problems must be 1 for this entry point (batched form: lddmm_register_batched).
+ */
+int lddmm_register(lddmm_problem *p, int32_t n_problems, const lddmm_params *params,
+                   void *stream);
+
+/*
+ * Energy of p->v on the single-level grid (n_levels ignored; h = grid.spacing):
+ * out4 (device, 4 doubles) = {E, R, D, image SSD}, with
+ *   R = dt h^3 sum_j sum_x |L v_j|^2 (periodic 7-point Laplacian),
+ *   D = h^3/sigma^2 sum_c w_c sum_x (J0c o phi_10 - J1c)^2,
+ *   image SSD = h^3 sum_x (M0I0 o phi_10 - M1I1)^2 (NaN without images).  Async.
+ */
+int lddmm_energy(const lddmm_problem *p, const lddmm_params *params, double *out4,
+                 void *stream);
+
+/*
+ * Gradient of E at p->v (single level): kind LDDMM_GRAD_V writes Beg's
+ * V-gradient 2 v_j - K b_j; kind LDDMM_GRAD_L2 writes the exact derivative of
+ * the discrete energy (reverse mode through the semi-Lagrangian sweep, with the
+ * adjoint of trilinear sampling).  grad is [T][3][P]; out4 as lddmm_energy.  Async.
+ */
+int lddmm_gradient(const lddmm_problem *p, const lddmm_params *params, int32_t kind,
+                   float *grad, double *out4, void *stream);
+
+/*
+ * Deform an image or a label map by a displacement (Methods, Postprocessing):
+ *   dst(x) = src(x + u(x)/h), u [3][N] in physical units, h = grid->spacing.
+ * LINEAR: trilinear, zero outside (dtype must be LDDMM_F32).
+ * NEAREST: src[floor(y + 1/2)], zero outside (LDDMM_F32 or LDDMM_I32 labels).  Async.
+ */
+int lddmm_apply(const lddmm_grid *grid, const float *u, const void *src, int32_t interp,
+                int32_t dtype, void *dst, void *stream);
+
+/*
+ * Apply K = (L^dagger L)^-1 (Methods, Registration) to a vector field on the
+ * computational grid P = {nx, ny, nz} (each axis 7-smooth) by a 3D DFT:
+ * out = IDFT((gamma + alpha lambda(k))^-2 DFT(b)), lambda the periodic 7-point
+ * Laplacian symbol with spacing h.  b, out [3][P] (may alias).  Workspace from
+ * lddmm_smooth_workspace_size.  Async.
+ */
+size_t lddmm_smooth_workspace_size(const int32_t P[3]);
+int lddmm_smooth(const int32_t P[3], double spacing, double alpha, double gamma,
+                 const float *b, float *out, void *workspace, size_t workspace_bytes,
+                 void *stream);
+
+/* Masks by threshold (Methods, Mask Generation): M = 1[I > tau], MI = M*I, on N. Async. */
+int lddmm_make_mask(const lddmm_grid *grid, const float *image, float tau, float *mask,
+                    float *masked_image, void *stream);
+
+/* Human-readable text of a status code (static storage). */
+const char *lddmm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDDMM_H */

@@ -1,0 +1,202 @@
+// Device-side control of gradient descent: energy reductions, the step guard
+// and the trace.  Keeping the accept/reject decision on the device lets the
+// host enqueue a whole level without synchronising.
+#include "device.h"
+
+namespace lddmm {
+
+__global__ void k_level_begin(State* st, double step, int keep_flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->mode = (keep_flags && st->nonfinite) ? MODE_STOPPED : MODE_INIT;
+  st->base = 0;
+  st->eval = 0;
+  st->halvings = 0;
+  if (!keep_flags) {
+    st->row = 0;
+    st->stopped_any = 0;
+    st->nonfinite = 0;
+    st->min_det_all = 1e300;
+  }
+  st->eps = step;
+  st->step0 = step;
+  st->min_det = __longlong_as_double(0x7ff8000000000000LL);   // NaN until a gradient is taken
+}
+
+void launch_level_begin(State* st, double step, int keep_flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(64), 0, s, st, step, keep_flags);
+}
+
+// Fixed-order sum of `count` partials by one 1024-thread block.
+__device__ double block1024_sum(const double* p, int count, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) v += p[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block1024_min(const double* p, int count, double* red) {
+  double v = 1e300;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) v = fmin(v, p[i]);
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Reduce the energy of the evaluated velocity and take the guard decision.
+//  init = 1 : first evaluation of a level (row 0), no decision.
+//  mode GRAD / RETRY : the slot evaluated a trial in buffer 1 - base.
+__global__ __launch_bounds__(1024) void k_decide(State* st, const double* partR, int T,
+                                                 const double* partD, const double* partI,
+                                                 const double* partDet, int nfw, int nbw,
+                                                 int has_img, double dt, double h3,
+                                                 double inv_sigma2, int guard, double* trace,
+                                                 int init) {
+  __shared__ double red[1024];
+  const int mode = st->mode;
+  if (mode == MODE_STOPPED) {
+    if (threadIdx.x == 0 && !init) {
+      double* row = trace + (long long)st->row * 8;
+      const double nan = __longlong_as_double(0x7ff8000000000000LL);
+      row[0] = nan;
+      row[1] = nan;
+      row[2] = nan;
+      row[3] = st->eps;
+      row[4] = st->min_det;
+      row[5] = nan;
+      row[6] = 0.0;
+      row[7] = st->E;
+      st->row += 1;
+    }
+    return;
+  }
+  double R = 0.0;
+  for (int j = 0; j < T; ++j) R += block1024_sum(partR + (long long)j * kPartMax, nfw, red);
+  const double D = block1024_sum(partD, nfw, red);
+  const double I = block1024_sum(partI, nfw, red);
+  double md = 0.0;
+  if (!init && mode == MODE_GRAD) {
+    md = 1e300;
+    for (int j = 0; j < T; ++j)
+      md = fmin(md, block1024_min(partDet + (long long)j * kPartMax, nbw, red));
+  }
+  if (threadIdx.x != 0) return;
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  const double Rt = dt * h3 * R;
+  const double Dt = h3 * inv_sigma2 * D;
+  const double It = has_img ? h3 * I : nan;
+  const double Et = Rt + Dt;
+  double* row = trace + (long long)st->row * 8;
+  if (init) {
+    st->E = Et;
+    st->R = Rt;
+    st->D = Dt;
+    st->img = It;
+    row[0] = Et;
+    row[1] = Rt;
+    row[2] = Dt;
+    row[3] = st->step0;
+    row[4] = nan;
+    row[5] = It;
+    row[6] = 1.0;
+    row[7] = Et;
+    st->row += 1;
+    if (!isfinite(Et)) {
+      st->nonfinite = 1;
+      st->mode = MODE_STOPPED;
+    } else {
+      st->mode = MODE_GRAD;
+      st->eval = 1 - st->base;
+    }
+    return;
+  }
+  if (mode == MODE_GRAD) {
+    st->min_det = md;
+    st->min_det_all = fmin(st->min_det_all, md);
+  }
+  const double used = st->eps;
+  const bool ok = !guard || (Et <= st->E);
+  if (ok) {
+    st->base = 1 - st->base;
+    st->E = Et;
+    st->R = Rt;
+    st->D = Dt;
+    st->img = It;
+    st->halvings = 0;
+    st->mode = MODE_GRAD;
+    if (!isfinite(Et)) {
+      st->nonfinite = 1;
+      st->mode = MODE_STOPPED;
+    }
+  } else {
+    st->eps = 0.5 * st->eps;
+    st->halvings += 1;
+    st->mode = MODE_RETRY;
+    if (st->halvings >= 10) {
+      st->mode = MODE_STOPPED;
+      st->stopped_any = 1;
+    }
+  }
+  st->eval = 1 - st->base;
+  row[0] = Et;
+  row[1] = Rt;
+  row[2] = Dt;
+  row[3] = used;
+  row[4] = st->min_det;
+  row[5] = It;
+  row[6] = ok ? 1.0 : 0.0;
+  row[7] = st->E;
+  st->row += 1;
+}
+
+void launch_decide(State* st, const double* partR, int T, const double* partD, const double* partI,
+                   const double* partDet, int nblk_fwd, int nblk_bwd, int has_img, double dt,
+                   double h3, double inv_sigma2, int guard, double* trace, int init,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, st, partR, T, partD, partI, partDet,
+                     nblk_fwd, nblk_bwd, has_img, dt, h3, inv_sigma2, guard, trace, init);
+}
+
+// After a rejection: trial <- (base + trial) / 2, i.e. v - eps g with the halved eps.
+__global__ __launch_bounds__(kBlock) void k_retry(float* vA, float* vB, long long count,
+                                                  const State* st) {
+  if (st->mode != MODE_RETRY) return;
+  const float* base = st->base ? vB : vA;
+  float* trial = st->base ? vA : vB;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < count;
+       i += (long long)gridDim.x * kBlock)
+    trial[i] = 0.5f * (base[i] + trial[i]);
+}
+
+void launch_retry(float* vA, float* vB, long long count, const State* st, hipStream_t s) {
+  long long b = (count + kBlock - 1) / kBlock;
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(k_retry, dim3((unsigned)b), dim3(kBlock), 0, s, vA, vB, count, st);
+}
+
+__global__ void k_energy_out(const State* st, double* out4) {
+  if (threadIdx.x == 0) {
+    out4[0] = st->E;
+    out4[1] = st->R;
+    out4[2] = st->D;
+    out4[3] = st->img;
+  }
+}
+
+void launch_energy_out(const State* st, double* out4, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_out, dim3(1), dim3(64), 0, s, st, out4);
+}
+
+}  // namespace lddmm

@@ -1,0 +1,416 @@
+// Flow kernels: forward sweep (inverse maps + deformed templates + energy
+// partials), backward sweep (forward maps + Jacobian + back-transported
+// residual + body force), pyramid transfer, padding, apply and masks.
+//
+// Discretisation (Methods, Registration; Beg et al. 2005 as cited there):
+//   u0_{j+1}(x) = -dt v_j(x) + S_clamp(u0_j; x - dt v_j(x)/h)
+//   J0_{j+1}(x) = S_zero(J0; x + u0_{j+1}(x)/h)
+//   u1_j(x)     =  dt v_j(x) + S_clamp(u1_{j+1}; x + dt v_j(x)/h)
+//   b_j(x)      = (2/sigma^2) det(I + D u1_j) sum_c w_c S_zero(r_c; x + u1_j/h) grad J0c_j
+// with u = phi - id in physical units (spacing h), positions in voxels.
+#include "device.h"
+
+namespace lddmm {
+
+int reduce_grid(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (int)(b < kPartMax ? (b < 1 ? 1 : b) : kPartMax);
+}
+
+static inline unsigned grid1d(long long n) {
+  long long b = (n + kBlock - 1) / kBlock;
+  if (b > (1LL << 30)) b = 1LL << 30;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ------------------------------------------------------------------ setup ----
+
+__global__ __launch_bounds__(kBlock) void k_pad(const float* __restrict__ src, int Nx, int Ny,
+                                                int Nz, float* __restrict__ dst, Geom g) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < g.n;
+       i += (long long)gridDim.x * kBlock) {
+    const int x = (int)(i % g.nx);
+    const long long t = i / g.nx;
+    const int y = (int)(t % g.ny);
+    const int z = (int)(t / g.ny);
+    float v = 0.f;
+    if (x < Nx && y < Ny && z < Nz) v = src[((long long)z * Ny + y) * Nx + x];
+    dst[i] = v;
+  }
+}
+
+void launch_pad(const float* src, int Nx, int Ny, int Nz, float* dst, const Geom& g,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_pad, dim3(grid1d(g.n)), dim3(kBlock), 0, s, src, Nx, Ny, Nz, dst, g);
+}
+
+// 2x block average, nfields consecutive planes of the fine grid.
+__global__ __launch_bounds__(kBlock) void k_down2(const float* __restrict__ src, Geom f,
+                                                  float* __restrict__ dst, Geom c, int nfields) {
+  const long long total = c.n * nfields;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+       i += (long long)gridDim.x * kBlock) {
+    const long long fld = i / c.n;
+    const long long k = i - fld * c.n;
+    const int x = (int)(k % c.nx);
+    const long long t = k / c.nx;
+    const int y = (int)(t % c.ny);
+    const int z = (int)(t / c.ny);
+    const float* p = src + fld * f.n + vidx(f, 2 * x, 2 * y, 2 * z);
+    const long long sy = f.nx, sz = (long long)f.nx * f.ny;
+    const float s = ((p[0] + p[1]) + (p[sy] + p[sy + 1])) + ((p[sz] + p[sz + 1]) + (p[sz + sy] + p[sz + sy + 1]));
+    dst[i] = 0.125f * s;
+  }
+}
+
+void launch_down2(const float* src, const Geom& fine, float* dst, const Geom& coarse, int nfields,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_down2, dim3(grid1d(coarse.n * nfields)), dim3(kBlock), 0, s, src, fine, dst,
+                     coarse, nfields);
+}
+
+// Cell-centred 2x trilinear upsample, coordinates clamped: fine i <-> coarse (i + 1/2)/2 - 1/2.
+__global__ __launch_bounds__(kBlock) void k_up2(const float* __restrict__ src, Geom c,
+                                                float* __restrict__ dst, Geom f, int nfields) {
+  const long long total = f.n * nfields;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total;
+       i += (long long)gridDim.x * kBlock) {
+    const long long fld = i / f.n;
+    const long long k = i - fld * f.n;
+    const int x = (int)(k % f.nx);
+    const long long t = k / f.nx;
+    const int y = (int)(t % f.ny);
+    const int z = (int)(t / f.ny);
+    // coarse position = x/2 - 1/4 = floor(x/2) + d with d = -1/4 (x even) or +1/4 (x odd)
+    int cx, cy, cz;
+    float fx, fy, fz;
+    cell_clamp(x >> 1, (x & 1) ? 0.25f : -0.25f, c.nx, cx, fx);
+    cell_clamp(y >> 1, (y & 1) ? 0.25f : -0.25f, c.ny, cy, fy);
+    cell_clamp(z >> 1, (z & 1) ? 0.25f : -0.25f, c.nz, cz, fz);
+    dst[i] = tri_clamped(src + fld * c.n, c, cx, cy, cz, fx, fy, fz);
+  }
+}
+
+void launch_up2(const float* src, const Geom& coarse, float* dst, const Geom& fine, int nfields,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_up2, dim3(grid1d(fine.n * nfields)), dim3(kBlock), 0, s, src, coarse, dst,
+                     fine, nfields);
+}
+
+// ---------------------------------------------------------- forward sweep ----
+
+template <int NC, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
+  const State* st = a.st;
+  if (st->mode == MODE_STOPPED) return;
+  const Geom g = a.g;
+  const long long n = g.n;
+  const float* __restrict__ v = (st->eval ? a.vB : a.vA) + (long long)a.j * 3 * n;
+  const float dt = a.dt, ih = g.inv_h;
+  const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+  double accR = 0.0, accD = 0.0, accI = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const int x = (int)(i % g.nx);
+    const long long t = i / g.nx;
+    const int y = (int)(t % g.ny);
+    const int z = (int)(t / g.ny);
+    const float vx = v[i], vy = v[i + n], vz = v[i + 2 * n];
+    float ux = -dt * vx, uy = -dt * vy, uz = -dt * vz;
+    if (!FIRST) {
+      int cx, cy, cz;
+      float fx, fy, fz;
+      cell_clamp(x, -dt * vx * ih, g.nx, cx, fx);
+      cell_clamp(y, -dt * vy * ih, g.ny, cy, fy);
+      cell_clamp(z, -dt * vz * ih, g.nz, cz, fz);
+      const float* __restrict__ u = a.u_cur;
+      ux += tri_clamped(u, g, cx, cy, cz, fx, fy, fz);
+      uy += tri_clamped(u + n, g, cx, cy, cz, fx, fy, fz);
+      uz += tri_clamped(u + 2 * n, g, cx, cy, cz, fx, fy, fz);
+    }
+    a.u_next[i] = ux;
+    a.u_next[i + n] = uy;
+    a.u_next[i + 2 * n] = uz;
+    // deformed templates at t_{j+1}
+    {
+      int cx, cy, cz;
+      float fx, fy, fz;
+      cell_free(x, ux * ih, g.nx, cx, fx);
+      cell_free(y, uy * ih, g.ny, cy, fy);
+      cell_free(z, uz * ih, g.nz, cz, fz);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float val = tri_zero(a.J0 + (long long)a.ch[c] * n, g, cx, cy, cz, fx, fy, fz);
+        if (!LAST) {
+          a.J0t_next[(long long)c * n + i] = val;
+        } else {
+          const float r = val - a.J1[(long long)a.ch[c] * n + i];
+          a.r[(long long)c * n + i] = r;
+          accD += (double)a.w[c] * (double)r * (double)r;
+          if (a.img_weighted && c == a.img_slot) accI += (double)r * (double)r;
+        }
+      }
+      if (LAST && a.img_ch >= 0 && !a.img_weighted) {
+        const float val = tri_zero(a.J0 + (long long)a.img_ch * n, g, cx, cy, cz, fx, fy, fz);
+        const float d = val - a.J1[(long long)a.img_ch * n + i];
+        accI += (double)d * (double)d;
+      }
+    }
+    // |L v_j|^2 with L = gamma - alpha Lap (periodic 7-point)
+    {
+      const float c2 = a.alpha * ih * ih;
+      const float lx = a.gamma * vx - c2 * lap7(v, g, i, x, y, z);
+      const float ly = a.gamma * vy - c2 * lap7(v + n, g, i, x, y, z);
+      const float lz = a.gamma * vz - c2 * lap7(v + 2 * n, g, i, x, y, z);
+      accR += (double)lx * lx + (double)ly * ly + (double)lz * lz;
+    }
+  }
+  (void)sy;
+  (void)sz;
+  const double sR = block_sum(accR);
+  if (threadIdx.x == 0) a.partR[blockIdx.x] = sR;
+  if (LAST) {
+    const double sD = block_sum(accD);
+    const double sI = block_sum(accI);
+    if (threadIdx.x == 0) {
+      a.partD[blockIdx.x] = sD;
+      a.partI[blockIdx.x] = sI;
+    }
+  }
+}
+
+template <int NC>
+static void fwd_dispatch(const FwdArgs& a, hipStream_t s) {
+  const int grid = reduce_grid(a.g.n);
+  const bool first = (a.j == 0), last = (a.j == a.T - 1);
+  if (first && last)
+    hipLaunchKernelGGL((k_forward<NC, true, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (first)
+    hipLaunchKernelGGL((k_forward<NC, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (last)
+    hipLaunchKernelGGL((k_forward<NC, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_forward<NC, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+}
+
+void launch_forward(const FwdArgs& a, hipStream_t s) {
+  if (a.nch == 2)
+    fwd_dispatch<2>(a, s);
+  else
+    fwd_dispatch<1>(a, s);
+}
+
+// --------------------------------------------------------- backward sweep ----
+
+template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
+__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
+  const State* st = a.st;
+  if (a.need_mode >= 0 && st->mode != a.need_mode) return;
+  const Geom g = a.g;
+  const long long n = g.n;
+  const float dt = a.dt, ih = g.inv_h;
+  const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+  const float* __restrict__ vb = a.vfix ? a.vfix : (st->base ? a.vB : a.vA);
+  double mind = 1e300;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const int x = (int)(i % g.nx);
+    const long long t = i / g.nx;
+    const int y = (int)(t % g.ny);
+    const int z = (int)(t / g.ny);
+    if (HAS_U) {
+      const float* __restrict__ v = vb + (long long)a.j * 3 * n;
+      const float vx = v[i], vy = v[i + n], vz = v[i + 2 * n];
+      float ux = dt * vx, uy = dt * vy, uz = dt * vz;
+      if (!UZERO) {
+        int cx, cy, cz;
+        float fx, fy, fz;
+        cell_clamp(x, dt * vx * ih, g.nx, cx, fx);
+        cell_clamp(y, dt * vy * ih, g.ny, cy, fy);
+        cell_clamp(z, dt * vz * ih, g.nz, cz, fz);
+        const float* __restrict__ u = a.u_next;
+        ux += tri_clamped(u, g, cx, cy, cz, fx, fy, fz);
+        uy += tri_clamped(u + n, g, cx, cy, cz, fx, fy, fz);
+        uz += tri_clamped(u + 2 * n, g, cx, cy, cz, fx, fy, fz);
+      }
+      a.u_cur[i] = ux;
+      a.u_cur[i + n] = uy;
+      a.u_cur[i + 2 * n] = uz;
+    }
+    if (HAS_B) {
+      const float* __restrict__ u = a.u_next;   // u1 at time jb
+      // Jacobian matrix I + D u (rows: component, columns: direction)
+      float J[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float* uc = u + c * n;
+        J[c][0] = dstencil(uc, i, x, g.nx, 1, ih);
+        J[c][1] = dstencil(uc, i, y, g.ny, sy, ih);
+        J[c][2] = dstencil(uc, i, z, g.nz, sz, ih);
+      }
+      J[0][0] += 1.f;
+      J[1][1] += 1.f;
+      J[2][2] += 1.f;
+      const float det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                        J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      mind = fmin(mind, (double)det);
+      int cx, cy, cz;
+      float fx, fy, fz;
+      cell_free(x, u[i] * ih, g.nx, cx, fx);
+      cell_free(y, u[i + n] * ih, g.ny, cy, fy);
+      cell_free(z, u[i + 2 * n] * ih, g.nz, cz, fz);
+      float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float rw = a.w[c] * tri_zero(a.r + (long long)c * n, g, cx, cy, cz, fx, fy, fz);
+        const float* Jc = a.J0t + (long long)c * a.cstride;
+        bx += rw * dstencil(Jc, i, x, g.nx, 1, ih);
+        by += rw * dstencil(Jc, i, y, g.ny, sy, ih);
+        bz += rw * dstencil(Jc, i, z, g.nz, sz, ih);
+      }
+      const float s = a.coef * det;
+      a.b[i] = s * bx;
+      a.b[i + n] = s * by;
+      a.b[i + 2 * n] = s * bz;
+    }
+  }
+  if (HAS_B) {
+    const double m = block_min(mind);
+    if (threadIdx.x == 0) a.partDet[blockIdx.x] = m;
+  }
+}
+
+template <int NC>
+static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
+  const int grid = reduce_grid(a.g.n);
+  const bool hu = a.j >= 0, uz = (a.u_next == nullptr), hb = (a.jb >= 0 && a.jb < a.T);
+  if (hu && uz && !hb)
+    hipLaunchKernelGGL((k_backward<NC, true, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (hu && !uz && hb)
+    hipLaunchKernelGGL((k_backward<NC, true, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (hu && !uz && !hb)
+    hipLaunchKernelGGL((k_backward<NC, true, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (!hu && hb)
+    hipLaunchKernelGGL((k_backward<NC, false, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+}
+
+void launch_backward(const BwdArgs& a, hipStream_t s) {
+  if (a.nch == 2)
+    bwd_dispatch<2>(a, s);
+  else
+    bwd_dispatch<1>(a, s);
+}
+
+// ------------------------------------------------------------ utilities ----
+
+__global__ __launch_bounds__(kBlock) void k_crop3(const float* __restrict__ u, Geom g, int Nx,
+                                                  int Ny, int Nz, float* __restrict__ out) {
+  const long long N = (long long)Nx * Ny * Nz;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < 3 * N;
+       i += (long long)gridDim.x * kBlock) {
+    const int c = (int)(i / N);
+    const long long k = i - c * N;
+    const int x = (int)(k % Nx);
+    const long long t = k / Nx;
+    const int y = (int)(t % Ny);
+    const int z = (int)(t / Ny);
+    out[i] = u[c * g.n + vidx(g, x, y, z)];
+  }
+}
+
+void launch_crop3(const float* u, const Geom& g, int Nx, int Ny, int Nz, float* out,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_crop3, dim3(grid1d(3LL * Nx * Ny * Nz)), dim3(kBlock), 0, s, u, g, Nx, Ny,
+                     Nz, out);
+}
+
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void k_apply(const float* __restrict__ u, Geom g,
+                                                  const TS* __restrict__ src, int interp,
+                                                  TS* __restrict__ dst) {
+  const long long n = g.n;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const int x = (int)(i % g.nx);
+    const long long t = i / g.nx;
+    const int y = (int)(t % g.ny);
+    const int z = (int)(t / g.ny);
+    const float dx = u[i] * g.inv_h, dy = u[i + n] * g.inv_h, dz = u[i + 2 * n] * g.inv_h;
+    if (interp == 0) {
+      int cx, cy, cz;
+      float fx, fy, fz;
+      cell_free(x, dx, g.nx, cx, fx);
+      cell_free(y, dy, g.ny, cy, fy);
+      cell_free(z, dz, g.nz, cz, fz);
+      dst[i] = (TS)tri_zero((const float*)src, g, cx, cy, cz, fx, fy, fz);
+    } else {
+      // nearest: index floor(y + 1/2) with y = i + d; rounding uses d alone
+      int cx, cy, cz;
+      float fx, fy, fz;
+      cell_free(x, dx + 0.5f, g.nx, cx, fx);
+      cell_free(y, dy + 0.5f, g.ny, cy, fy);
+      cell_free(z, dz + 0.5f, g.nz, cz, fz);
+      const bool ok = (unsigned)cx < (unsigned)g.nx && (unsigned)cy < (unsigned)g.ny &&
+                      (unsigned)cz < (unsigned)g.nz;
+      dst[i] = ok ? src[vidx(g, cx, cy, cz)] : (TS)0;
+    }
+  }
+}
+
+void launch_apply(const float* u, int Nx, int Ny, int Nz, float inv_h, const void* src, int interp,
+                  int dtype, void* dst, hipStream_t s) {
+  Geom g{};
+  g.nx = Nx;
+  g.ny = Ny;
+  g.nz = Nz;
+  g.n = (long long)Nx * Ny * Nz;
+  g.inv_h = inv_h;
+  g.h = 1.f / inv_h;
+  if (dtype == 1)
+    hipLaunchKernelGGL(k_apply<int>, dim3(grid1d(g.n)), dim3(kBlock), 0, s, u, g,
+                       (const int*)src, interp, (int*)dst);
+  else
+    hipLaunchKernelGGL(k_apply<float>, dim3(grid1d(g.n)), dim3(kBlock), 0, s, u, g,
+                       (const float*)src, interp, (float*)dst);
+}
+
+__global__ __launch_bounds__(kBlock) void k_make_mask(const float* __restrict__ img, long long n,
+                                                      float tau, float* __restrict__ m,
+                                                      float* __restrict__ mi) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const float v = img[i];
+    const float k = v > tau ? 1.f : 0.f;
+    m[i] = k;
+    if (mi) mi[i] = k * v;
+  }
+}
+
+void launch_make_mask(const float* img, long long n, float tau, float* m, float* mi,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_make_mask, dim3(grid1d(n)), dim3(kBlock), 0, s, img, n, tau, m, mi);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(float* __restrict__ p, long long n, float val) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    p[i] = val;
+}
+
+void launch_fill(float* p, long long n, float val, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(kBlock), 0, s, p, n, val);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const float* __restrict__ a, float* __restrict__ b,
+                                                 long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    b[i] = a[i];
+}
+
+void launch_copy(const float* src, float* dst, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(kBlock), 0, s, src, dst, n);
+}
+
+}  // namespace lddmm

@@ -1,0 +1,156 @@
+// Internal declarations shared by the HIP kernel files and the host runtime.
+// Not part of the public C ABI (include/lddmm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lddmm {
+
+constexpr int kBlock = 256;        // threads per block for every kernel
+constexpr int kPartMax = 1024;     // max blocks of a reducing kernel (partials per launch)
+constexpr int kMaxStages = 12;     // radix stages of one 1D transform
+constexpr int kFFTElems = 4096;    // complex values held in LDS by one FFT block (32 KB)
+constexpr int kEMax = 16;          // complex values one thread holds across an LDS stage
+
+// Computational grid of one pyramid level.
+struct Geom {
+  int nx, ny, nz;   // P (each axis 7-smooth)
+  int hx;           // nx/2 + 1: length of the half spectrum along x
+  long long n;      // nx*ny*nz
+  long long nspec;  // hx*ny*nz
+  float h, inv_h;   // spacing and its inverse
+};
+
+// Mixed-radix factorisation of one transform length (radices 2,3,4,5,7,8).
+struct FFTPlan {
+  int n, nst;
+  int radix[kMaxStages];
+};
+
+// Device-side control state of the descent (one per problem).
+enum : int { MODE_GRAD = 0, MODE_RETRY = 1, MODE_STOPPED = 2, MODE_INIT = 3 };
+
+struct State {
+  int mode;        // what the next slot does
+  int base;        // v buffer holding the current iterate
+  int eval;        // v buffer the forward sweep evaluates
+  int halvings;    // consecutive rejections
+  int row;         // next trace row
+  int stopped_any; // a level stopped on the guard
+  int nonfinite;   // non-finite energy seen
+  int pad0;
+  double eps, step0;
+  double E, R, D, img;       // energy terms of the current iterate
+  double min_det, min_det_all;
+};
+
+// --------------------------------------------------------------- sweeps ----
+
+struct FwdArgs {
+  Geom g;
+  const float* vA;        // v buffers [T][3][n]; st->eval selects one
+  const float* vB;
+  int j, T;
+  float dt, alpha, gamma;
+  const float* u_cur;     // u0_j [3][n] (unused when j == 0)
+  float* u_next;          // u0_{j+1} [3][n]
+  const float* J0;        // template channels [C][n]
+  const float* J1;        // target channels [C][n]
+  int nch;                // weighted channels (1 or 2)
+  int ch[2];              // their channel index in J0/J1
+  float w[2];             // their weights
+  int img_ch;             // image channel index for the monitor (-1: none)
+  int img_weighted;       // 1 if img_ch is among the weighted channels (slot img_slot)
+  int img_slot;
+  float* J0t_next;        // deformed templates at j+1 [nch][n] (j+1 < T)
+  float* r;               // residual [nch][n] (j+1 == T)
+  double* partR;          // [kPartMax] for this j
+  double* partD;          // [kPartMax]
+  double* partI;          // [kPartMax]
+  const State* st;
+};
+
+struct BwdArgs {
+  Geom g;
+  const float* vA;
+  const float* vB;        // st->base selects the iterate
+  const float* vfix;      // if non-null: use this v instead of vA/vB
+  int T;
+  float dt;
+  int j;                  // u1_j from u1_{j+1} (j >= 0), else no map step
+  const float* u_next;    // u1_{j+1} [3][n] (null: zero)
+  float* u_cur;           // u1_j [3][n]
+  int jb;                 // body force at time jb = j+1 (< T), else none
+  const float* J0t;       // deformed templates at jb, channel stride cstride
+  long long cstride;
+  const float* r;         // residual [nch][n]
+  int nch;
+  float w[2];
+  float coef;             // 2 / sigma^2
+  float* b;               // out: body force [3][n]
+  double* partDet;        // [kPartMax] min det per block
+  const State* st;
+  int need_mode;          // run only when st->mode == need_mode (-1: always)
+};
+
+// x-inverse pass epilogue
+enum : int { UPD_STEP = 0, UPD_WRITE_G = 1, UPD_WRITE_KB = 2 };
+
+struct UpdArgs {
+  int kind;
+  int j;                  // time step of v
+  float* vA;              // v buffers [T][3][n]
+  float* vB;
+  const float* vfix;      // UPD_WRITE_G with an explicit v
+  float* out;             // UPD_WRITE_G: g [T][3][n]; UPD_WRITE_KB: Kb [3][n]
+  const State* st;
+  int need_mode;
+};
+
+// --------------------------------------------------------------- launchers --
+// flow.hip
+void launch_pad(const float* src, int Nx, int Ny, int Nz, float* dst, const Geom& g,
+                hipStream_t s);
+void launch_down2(const float* src, const Geom& fine, float* dst, const Geom& coarse,
+                  int nfields, hipStream_t s);
+void launch_up2(const float* src, const Geom& coarse, float* dst, const Geom& fine, int nfields,
+                hipStream_t s);
+int reduce_grid(long long n);
+void launch_forward(const FwdArgs& a, hipStream_t s);
+void launch_backward(const BwdArgs& a, hipStream_t s);
+void launch_crop3(const float* u, const Geom& g, int Nx, int Ny, int Nz, float* out,
+                  hipStream_t s);
+void launch_apply(const float* u, int Nx, int Ny, int Nz, float inv_h, const void* src,
+                  int interp, int dtype, void* dst, hipStream_t s);
+void launch_make_mask(const float* img, long long n, float tau, float* m, float* mi,
+                      hipStream_t s);
+void launch_fill(float* p, long long n, float val, hipStream_t s);
+void launch_copy(const float* src, float* dst, long long n, hipStream_t s);
+
+// fft.hip
+bool make_plan(int n, FFTPlan* p);
+void launch_twiddles(float2* tw, int n, hipStream_t s);
+void launch_lambda(double* lam, int n, double h, hipStream_t s);
+void launch_fft_x_fwd(const float* b, float2* S, const Geom& g, const FFTPlan& p,
+                      const float2* tw, const State* st, int need_mode, hipStream_t s);
+void launch_fft_y(float2* S, const Geom& g, const FFTPlan& p, const float2* tw, int inverse,
+                  const State* st, int need_mode, hipStream_t s);
+void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
+                    const double* lamx, const double* lamy, const double* lamz, double alpha,
+                    double gamma, const State* st, int need_mode, hipStream_t s);
+void launch_fft_x_inv(const float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
+                      const UpdArgs& u, hipStream_t s);
+
+// control.hip
+void launch_level_begin(State* st, double step, int keep_flags, hipStream_t s);
+void launch_decide(State* st, const double* partR, int T, const double* partD,
+                   const double* partI, const double* partDet, int nblk_fwd, int nblk_bwd,
+                   int has_img, double dt, double h3, double inv_sigma2, int guard,
+                   double* trace, int init, hipStream_t s);
+void launch_retry(float* vA, float* vB, long long count, const State* st, hipStream_t s);
+void launch_energy_out(const State* st, double* out4, hipStream_t s);
+
+}  // namespace lddmm

@@ -1,0 +1,656 @@
+// Host runtime behind the C ABI (include/lddmm.h): argument checks, pyramid
+// geometry, workspace layout, and the launch sequence of the descent.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+#include "lddmm.h"
+
+namespace lddmm {
+
+static bool is_7smooth(int n) {
+  for (int p : {2, 3, 5, 7})
+    while (n > 1 && n % p == 0) n /= p;
+  return n == 1;
+}
+
+static int smooth7(int n) {
+  int m = n < 2 ? 2 : n;
+  while (!is_7smooth(m)) ++m;
+  return m;
+}
+
+struct Level {
+  Geom g;
+  int N[3];          // user grid of this level (x, y, z)
+  FFTPlan px, py, pz;
+};
+
+static Geom make_geom(int nx, int ny, int nz, double h) {
+  Geom g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.hx = nx / 2 + 1;
+  g.n = (long long)nx * ny * nz;
+  g.nspec = (long long)g.hx * ny * nz;
+  g.h = (float)h;
+  g.inv_h = (float)(1.0 / h);
+  return g;
+}
+
+// Levels coarsest first; the coarsest computational grid is 7-smooth and each
+// finer one doubles it, so all levels nest.
+static bool build_levels(const lddmm_grid* grid, int L, Level* lv) {
+  const int N[3] = {grid->nx, grid->ny, grid->nz};
+  const int f = 1 << (L - 1);
+  int Pc[3];
+  for (int d = 0; d < 3; ++d) Pc[d] = smooth7((N[d] + f - 1) / f);
+  for (int li = 0; li < L; ++li) {
+    const int lev = L - 1 - li;        // 0 = finest
+    const int s = 1 << lev;
+    int P[3];
+    for (int d = 0; d < 3; ++d) {
+      P[d] = Pc[d] * (f / s);
+      lv[li].N[d] = (N[d] + s - 1) / s;
+      if (P[d] < 2 || P[d] > LDDMM_MAX_DIM) return false;
+    }
+    lv[li].g = make_geom(P[0], P[1], P[2], grid->spacing * (double)s);
+    if (!make_plan(P[0], &lv[li].px) || !make_plan(P[1], &lv[li].py) ||
+        !make_plan(P[2], &lv[li].pz))
+      return false;
+  }
+  return true;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t state, partR, partD, partI, partDet, trace, tw[3], lam[3];
+  size_t J0, J1, v0, v1, u0, u1, J0t, r, b, S, ub, total;
+  size_t Joff[LDDMM_MAX_LEVELS];   // per-level offsets (floats) inside J0 / J1
+  int n_u0;                         // u0 slots
+};
+
+struct Config {
+  int L, T, C, nch, ch[2];
+  float w[2];
+  int img_ch, img_weighted, img_slot;
+  Level lv[LDDMM_MAX_LEVELS];
+  int rows;
+};
+
+static int trace_rows(const lddmm_params* p) {
+  int rows = 0;
+  for (int l = 0; l < p->n_levels; ++l) rows += p->iters[l] + 1;
+  return rows;
+}
+
+static int check_params(const lddmm_grid* grid, const lddmm_params* p, int multilevel) {
+  if (!grid || !p) return LDDMM_EINVAL;
+  if (grid->nx < 2 || grid->ny < 2 || grid->nz < 2) return LDDMM_EINVAL;
+  if (grid->nx > LDDMM_MAX_DIM || grid->ny > LDDMM_MAX_DIM || grid->nz > LDDMM_MAX_DIM)
+    return LDDMM_EINVAL;
+  if (!(grid->spacing > 0.0) || !std::isfinite(grid->spacing)) return LDDMM_EINVAL;
+  if (!(p->alpha >= 0.0) || !(p->gamma > 0.0) || !(p->sigma > 0.0)) return LDDMM_EINVAL;
+  if (!std::isfinite(p->alpha) || !std::isfinite(p->gamma) || !std::isfinite(p->sigma))
+    return LDDMM_EINVAL;
+  if (p->n_timesteps < 1 || p->n_timesteps > LDDMM_MAX_T) return LDDMM_EINVAL;
+  if (multilevel) {
+    if (p->n_levels < 1 || p->n_levels > LDDMM_MAX_LEVELS) return LDDMM_EINVAL;
+    for (int l = 0; l < p->n_levels; ++l)
+      if (p->iters[l] < 0 || p->iters[l] > 1000000) return LDDMM_EINVAL;
+    if (!(p->step > 0.0) || !std::isfinite(p->step)) return LDDMM_EINVAL;
+  }
+  if (!(p->weight[0] >= 0.0) || !(p->weight[1] >= 0.0)) return LDDMM_EINVAL;
+  return LDDMM_OK;
+}
+
+static int make_config(const lddmm_grid* grid, const lddmm_params* p, int has_img, int multilevel,
+                       Config* c) {
+  int rc = check_params(grid, p, multilevel);
+  if (rc) return rc;
+  c->L = multilevel ? p->n_levels : 1;
+  c->T = p->n_timesteps;
+  c->C = has_img ? 2 : 1;
+  c->nch = 0;
+  for (int k = 0; k < c->C; ++k) {
+    if (p->weight[k] > 0.0) {
+      c->ch[c->nch] = k;
+      c->w[c->nch] = (float)p->weight[k];
+      ++c->nch;
+    }
+  }
+  if (c->nch == 0) return LDDMM_EINVAL;
+  c->img_ch = has_img ? 1 : -1;
+  c->img_weighted = 0;
+  c->img_slot = 0;
+  for (int k = 0; k < c->nch; ++k)
+    if (c->ch[k] == 1) {
+      c->img_weighted = 1;
+      c->img_slot = k;
+    }
+  if (!build_levels(grid, c->L, c->lv)) return LDDMM_EINVAL;
+  c->rows = multilevel ? trace_rows(p) : 1;
+  return LDDMM_OK;
+}
+
+static Layout make_layout(const Config& c) {
+  Layout o{};
+  const Geom& gf = c.lv[c.L - 1].g;
+  const size_t n = (size_t)gf.n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off);
+    const size_t at = off;
+    off += bytes;
+    return at;
+  };
+  o.state = take(sizeof(State));
+  o.partR = take(sizeof(double) * kPartMax * c.T);
+  o.partD = take(sizeof(double) * kPartMax);
+  o.partI = take(sizeof(double) * kPartMax);
+  o.partDet = take(sizeof(double) * kPartMax * c.T);
+  o.trace = take(sizeof(double) * 8 * (size_t)(c.rows > 0 ? c.rows : 1));
+  const int P[3] = {gf.nx, gf.ny, gf.nz};
+  for (int d = 0; d < 3; ++d) o.tw[d] = take(sizeof(float2) * P[d]);
+  for (int d = 0; d < 3; ++d) o.lam[d] = take(sizeof(double) * P[d]);
+  size_t jt = 0;
+  for (int l = 0; l < c.L; ++l) {
+    o.Joff[l] = jt;
+    jt += (size_t)c.C * c.lv[l].g.n;
+  }
+  o.J0 = take(sizeof(float) * jt);
+  o.J1 = take(sizeof(float) * jt);
+  o.v0 = take(sizeof(float) * 3 * n * c.T);
+  o.v1 = take(sizeof(float) * 3 * n * c.T);
+  o.n_u0 = c.T + 1;
+  o.u0 = take(sizeof(float) * 3 * n * o.n_u0);
+  o.u1 = take(sizeof(float) * 3 * n * 2);
+  o.J0t = take(sizeof(float) * n * c.nch * c.T);
+  o.r = take(sizeof(float) * n * c.nch);
+  o.b = take(sizeof(float) * 3 * n);
+  o.S = take(sizeof(float2) * 3 * (size_t)gf.nspec);
+  o.ub = take(sizeof(float) * 3 * n * 2);
+  o.total = align_up(off);
+  return o;
+}
+
+// Device pointers of one problem's workspace at one level.
+struct Ctx {
+  Config cfg;
+  Layout lay;
+  char* ws;
+  State* st;
+  double *partR, *partD, *partI, *partDet, *trace;
+  float2* tw[3];
+  double* lam[3];
+  float *J0, *J1, *v[2], *u0, *u1, *J0t, *r, *b, *ub;
+  float2* S;
+  double alpha, gamma, sigma;
+  int guard;
+};
+
+static void bind(Ctx& c, void* ws) {
+  c.ws = (char*)ws;
+  const Layout& o = c.lay;
+  c.st = (State*)(c.ws + o.state);
+  c.partR = (double*)(c.ws + o.partR);
+  c.partD = (double*)(c.ws + o.partD);
+  c.partI = (double*)(c.ws + o.partI);
+  c.partDet = (double*)(c.ws + o.partDet);
+  c.trace = (double*)(c.ws + o.trace);
+  for (int d = 0; d < 3; ++d) {
+    c.tw[d] = (float2*)(c.ws + o.tw[d]);
+    c.lam[d] = (double*)(c.ws + o.lam[d]);
+  }
+  c.J0 = (float*)(c.ws + o.J0);
+  c.J1 = (float*)(c.ws + o.J1);
+  c.v[0] = (float*)(c.ws + o.v0);
+  c.v[1] = (float*)(c.ws + o.v1);
+  c.u0 = (float*)(c.ws + o.u0);
+  c.u1 = (float*)(c.ws + o.u1);
+  c.J0t = (float*)(c.ws + o.J0t);
+  c.r = (float*)(c.ws + o.r);
+  c.b = (float*)(c.ws + o.b);
+  c.S = (float2*)(c.ws + o.S);
+  c.ub = (float*)(c.ws + o.ub);
+}
+
+static void level_tables(Ctx& c, const Level& L, hipStream_t s) {
+  const int P[3] = {L.g.nx, L.g.ny, L.g.nz};
+  for (int d = 0; d < 3; ++d) {
+    launch_twiddles(c.tw[d], P[d], s);
+    launch_lambda(c.lam[d], P[d], (double)L.g.h, s);
+  }
+}
+
+// Forward sweep of the velocity selected by st->eval (vA/vB), storing u0 in
+// ping-pong slots (or all T+1 slots when keep_all), deformed templates and r.
+static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool keep_all,
+                          hipStream_t s) {
+  const Config& k = c.cfg;
+  const Level& L = k.lv[li];
+  const long long n = L.g.n;
+  for (int j = 0; j < k.T; ++j) {
+    FwdArgs a{};
+    a.g = L.g;
+    a.vA = vA;
+    a.vB = vB;
+    a.j = j;
+    a.T = k.T;
+    a.dt = 1.0f / (float)k.T;
+    a.alpha = (float)c.alpha;
+    a.gamma = (float)c.gamma;
+    const int sc = keep_all ? j : (j & 1), sn = keep_all ? j + 1 : ((j + 1) & 1);
+    a.u_cur = c.u0 + (long long)sc * 3 * n;
+    a.u_next = c.u0 + (long long)sn * 3 * n;
+    a.J0 = c.J0 + c.lay.Joff[li];
+    a.J1 = c.J1 + c.lay.Joff[li];
+    a.nch = k.nch;
+    a.ch[0] = k.ch[0];
+    a.ch[1] = k.nch > 1 ? k.ch[1] : k.ch[0];
+    a.w[0] = k.w[0];
+    a.w[1] = k.nch > 1 ? k.w[1] : 0.f;
+    a.img_ch = k.img_ch;
+    a.img_weighted = k.img_weighted;
+    a.img_slot = k.img_slot;
+    a.J0t_next = c.J0t + (long long)(j + 1) * k.nch * n;
+    a.r = c.r;
+    a.partR = c.partR + (long long)j * kPartMax;
+    a.partD = c.partD;
+    a.partI = c.partI;
+    a.st = c.st;
+    launch_forward(a, s);
+  }
+}
+
+static float* u0_final(Ctx& c, int li, bool keep_all) {
+  const long long n = c.cfg.lv[li].g.n;
+  const int T = c.cfg.T;
+  return c.u0 + (long long)(keep_all ? T : (T & 1)) * 3 * n;
+}
+
+// K smoothing of c.b followed by the x-inverse epilogue.
+static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, hipStream_t s) {
+  const Level& L = c.cfg.lv[li];
+  launch_fft_x_fwd(c.b, c.S, L.g, L.px, c.tw[0], c.st, need_mode, s);
+  launch_fft_y(c.S, L.g, L.py, c.tw[1], 0, c.st, need_mode, s);
+  launch_fft_z_K(c.S, L.g, L.pz, c.tw[2], c.lam[0], c.lam[1], c.lam[2], c.alpha, c.gamma, c.st,
+                 need_mode, s);
+  launch_fft_y(c.S, L.g, L.py, c.tw[1], 1, c.st, need_mode, s);
+  launch_fft_x_inv(c.S, L.g, L.px, c.tw[0], u, s);
+}
+
+// Backward sweep: maps u1_j, body forces b_j, K b_j and the epilogue per j.
+// With with_grad = false only the maps are computed (u1_0 ends in slot 0).
+static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vfix, bool with_grad,
+                           int upd_kind, float* gout, int need_mode, hipStream_t s) {
+  const Config& k = c.cfg;
+  const Level& L = k.lv[li];
+  const long long n = L.g.n;
+  for (int j = k.T - 1; j >= (with_grad ? -1 : 0); --j) {
+    BwdArgs a{};
+    a.g = L.g;
+    a.vA = vA;
+    a.vB = vB;
+    a.vfix = vfix;
+    a.T = k.T;
+    a.dt = 1.0f / (float)k.T;
+    a.j = j;
+    a.u_next = (j == k.T - 1) ? nullptr : c.u1 + (long long)((j + 1) & 1) * 3 * n;
+    a.u_cur = j >= 0 ? c.u1 + (long long)(j & 1) * 3 * n : nullptr;
+    const int jb = j + 1;
+    a.jb = (with_grad && jb <= k.T - 1) ? jb : -1;
+    if (a.jb == 0) {
+      a.J0t = c.J0 + c.lay.Joff[li] + (long long)k.ch[0] * n;
+      a.cstride = k.nch > 1 ? (long long)(k.ch[1] - k.ch[0]) * n : n;
+    } else {
+      a.J0t = c.J0t + (long long)jb * k.nch * n;
+      a.cstride = n;
+    }
+    a.r = c.r;
+    a.nch = k.nch;
+    a.w[0] = k.w[0];
+    a.w[1] = k.nch > 1 ? k.w[1] : 0.f;
+    a.coef = (float)(2.0 / (c.sigma * c.sigma));
+    a.b = c.b;
+    a.partDet = c.partDet + (long long)(a.jb >= 0 ? a.jb : 0) * kPartMax;
+    a.st = c.st;
+    a.need_mode = need_mode;
+    if (a.j < 0 && a.jb < 0) continue;
+    launch_backward(a, s);
+    if (a.jb >= 0) {
+      UpdArgs u{};
+      u.kind = upd_kind;
+      u.j = a.jb;
+      u.vA = vA;
+      u.vB = vB;
+      u.vfix = vfix;
+      u.out = gout;
+      u.st = c.st;
+      u.need_mode = need_mode;
+      smooth_and_update(c, li, u, need_mode, s);
+    }
+  }
+}
+
+static void decide(Ctx& c, int li, int init, double* trace, hipStream_t s) {
+  const Level& L = c.cfg.lv[li];
+  const int nb = reduce_grid(L.g.n);
+  const double h = (double)L.g.h;
+  launch_decide(c.st, c.partR, c.cfg.T, c.partD, c.partI, c.partDet, nb, nb, c.cfg.C > 1,
+                1.0 / c.cfg.T, h * h * h, 1.0 / (c.sigma * c.sigma), c.guard, trace, init, s);
+}
+
+// Copy the current iterate into buffer 0 (kernel reads st->base).
+__global__ void k_canon(float* v0, const float* v1, long long count, const State* st) {
+  if (st->base == 0) return;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    v0[i] = v1[i];
+}
+
+__global__ void k_set_base(State* st, int base, int mode) {
+  if (threadIdx.x == 0) {
+    st->base = base;
+    st->eval = base;
+    if (mode >= 0) st->mode = mode;
+  }
+}
+
+static void canonicalize(Ctx& c, long long count, hipStream_t s) {
+  long long b = (count + 255) / 256;
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(k_canon, dim3((unsigned)b), dim3(256), 0, s, c.v[0], c.v[1], count, c.st);
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, c.st, 0, -1);
+}
+
+static void setup_images(Ctx& c, const lddmm_problem* p, hipStream_t s) {
+  const Config& k = c.cfg;
+  const int top = k.L - 1;
+  const Geom& gf = k.lv[top].g;
+  const int* N = k.lv[top].N;
+  float* J0f = c.J0 + c.lay.Joff[top];
+  float* J1f = c.J1 + c.lay.Joff[top];
+  launch_pad(p->template_mask, N[0], N[1], N[2], J0f, gf, s);
+  launch_pad(p->target_mask, N[0], N[1], N[2], J1f, gf, s);
+  if (k.C > 1) {
+    launch_pad(p->template_image, N[0], N[1], N[2], J0f + gf.n, gf, s);
+    launch_pad(p->target_image, N[0], N[1], N[2], J1f + gf.n, gf, s);
+  }
+  for (int li = top - 1; li >= 0; --li) {
+    launch_down2(c.J0 + c.lay.Joff[li + 1], k.lv[li + 1].g, c.J0 + c.lay.Joff[li], k.lv[li].g, k.C,
+                 s);
+    launch_down2(c.J1 + c.lay.Joff[li + 1], k.lv[li + 1].g, c.J1 + c.lay.Joff[li], k.lv[li].g, k.C,
+                 s);
+  }
+}
+
+static int check_problem(const lddmm_problem* p) {
+  if (!p || !p->template_mask || !p->target_mask || !p->v || !p->workspace) return LDDMM_EINVAL;
+  if ((p->template_image == nullptr) != (p->target_image == nullptr)) return LDDMM_EINVAL;
+  return LDDMM_OK;
+}
+
+static int hip_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LDDMM_OK : LDDMM_EHIP;
+}
+
+static int prepare(Ctx& c, const lddmm_problem* p, const lddmm_params* prm, int multilevel) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  rc = make_config(&p->grid, prm, p->template_image != nullptr, multilevel, &c.cfg);
+  if (rc) return rc;
+  c.lay = make_layout(c.cfg);
+  if (p->workspace_bytes < c.lay.total) return LDDMM_EINVAL;
+  bind(c, p->workspace);
+  c.alpha = prm->alpha;
+  c.gamma = prm->gamma;
+  c.sigma = prm->sigma;
+  c.guard = prm->guard ? 1 : 0;
+  return LDDMM_OK;
+}
+
+}  // namespace lddmm
+
+using namespace lddmm;
+
+extern "C" {
+
+size_t lddmm_workspace_size(const lddmm_grid* grid, const lddmm_params* params) {
+  Config c{};
+  if (make_config(grid, params, 1, 1, &c) != LDDMM_OK) {
+    // single-level use (energy/gradient) with unchecked descent fields
+    if (make_config(grid, params, 1, 0, &c) != LDDMM_OK) return 0;
+  }
+  Config c1 = c;
+  c1.nch = 2;   // size for the largest channel configuration
+  return make_layout(c1).total;
+}
+
+int lddmm_comp_grid(const lddmm_grid* grid, const lddmm_params* params, int32_t level,
+                    int32_t out_P[3]) {
+  if (!out_P) return LDDMM_EINVAL;
+  int rc = check_params(grid, params, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= params->n_levels) return LDDMM_EINVAL;
+  Level lv[LDDMM_MAX_LEVELS];
+  if (!build_levels(grid, params->n_levels, lv)) return LDDMM_EINVAL;
+  const Geom& g = lv[params->n_levels - 1 - level].g;
+  out_P[0] = g.nx;
+  out_P[1] = g.ny;
+  out_P[2] = g.nz;
+  return LDDMM_OK;
+}
+
+int32_t lddmm_trace_rows(const lddmm_params* params) {
+  if (!params || params->n_levels < 1 || params->n_levels > LDDMM_MAX_LEVELS) return 0;
+  return trace_rows(params);
+}
+
+int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm, void* stream) {
+  if (n_problems != 1) return LDDMM_EINVAL;
+  Ctx c{};
+  int rc = prepare(c, p, prm, 1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipGetLastError();
+  const Config& k = c.cfg;
+  const int top = k.L - 1;
+  const long long nf = k.lv[top].g.n;
+  double* trace = p->trace ? p->trace : c.trace;
+
+  setup_images(c, p, s);
+  // initial velocity at the coarsest level: block-average the finest one down
+  {
+    const float* src = p->v;
+    int dst = 1;
+    for (int li = top - 1; li >= 0; --li) {
+      launch_down2(src, k.lv[li + 1].g, c.v[dst], k.lv[li].g, 3 * k.T, s);
+      src = c.v[dst];
+      dst ^= 1;
+    }
+    launch_copy(src, c.v[0], 3 * k.lv[0].g.n * k.T, s);
+  }
+  launch_level_begin(c.st, prm->step, 0, s);
+  for (int li = 0; li <= top; ++li) {
+    const Level& L = k.lv[li];
+    if (li > 0) {
+      // iterate of the previous level -> buffer 0, upsample into buffer 1
+      canonicalize(c, 3 * k.lv[li - 1].g.n * k.T, s);
+      launch_up2(c.v[0], k.lv[li - 1].g, c.v[1], L.g, 3 * k.T, s);
+      launch_copy(c.v[1], c.v[0], 3 * L.g.n * k.T, s);
+      launch_level_begin(c.st, prm->step, 1, s);
+    }
+    level_tables(c, L, s);
+    forward_sweep(c, li, c.v[0], c.v[1], false, s);
+    decide(c, li, 1, trace, s);
+    for (int it = 0; it < prm->iters[li]; ++it) {
+      backward_sweep(c, li, c.v[0], c.v[1], nullptr, true, UPD_STEP, nullptr, MODE_GRAD, s);
+      launch_retry(c.v[0], c.v[1], 3 * L.g.n * k.T, c.st, s);
+      forward_sweep(c, li, c.v[0], c.v[1], false, s);
+      decide(c, li, 0, trace, s);
+    }
+  }
+  // outputs from the final iterate
+  canonicalize(c, 3 * nf * k.T, s);
+  launch_copy(c.v[0], p->v, 3 * nf * k.T, s);
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, c.st, 0, (int)MODE_INIT);
+  if (p->phi10) {
+    forward_sweep(c, top, c.v[0], c.v[1], false, s);
+    launch_crop3(u0_final(c, top, false), k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1],
+                 k.lv[top].N[2], p->phi10, s);
+  }
+  if (p->phi01) {
+    backward_sweep(c, top, c.v[0], c.v[1], c.v[0], false, UPD_STEP, nullptr, -1, s);
+    launch_crop3(c.u1, k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1], k.lv[top].N[2], p->phi01, s);
+  }
+  rc = hip_status();
+  if (rc) return rc;
+  State hs{};
+  if (hipMemcpyAsync(&hs, c.st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return LDDMM_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return LDDMM_EHIP;
+  if (hs.nonfinite) {
+    const long long N3 = 3LL * k.lv[top].N[0] * k.lv[top].N[1] * k.lv[top].N[2];
+    if (p->phi10) launch_fill(p->phi10, N3, NAN, s);
+    if (p->phi01) launch_fill(p->phi01, N3, NAN, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return LDDMM_EHIP;
+    return LDDMM_ENONFINITE;
+  }
+  if (hs.stopped_any) return LDDMM_WGUARD;
+  if (hs.min_det_all <= 0.0) return LDDMM_WFOLD;
+  return LDDMM_OK;
+}
+
+int lddmm_energy(const lddmm_problem* p, const lddmm_params* prm, double* out4, void* stream) {
+  if (!out4) return LDDMM_EINVAL;
+  Ctx c{};
+  int rc = prepare(c, p, prm, 0);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipGetLastError();
+  setup_images(c, p, s);
+  launch_level_begin(c.st, 1.0, 0, s);
+  level_tables(c, c.cfg.lv[0], s);
+  forward_sweep(c, 0, p->v, p->v, false, s);
+  decide(c, 0, 1, c.trace, s);
+  launch_energy_out(c.st, out4, s);
+  return hip_status();
+}
+
+int lddmm_gradient(const lddmm_problem* p, const lddmm_params* prm, int32_t kind, float* grad,
+                   double* out4, void* stream) {
+  if (!grad || !out4) return LDDMM_EINVAL;
+  if (kind != LDDMM_GRAD_V) return LDDMM_EINVAL;
+  Ctx c{};
+  int rc = prepare(c, p, prm, 0);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipGetLastError();
+  setup_images(c, p, s);
+  launch_level_begin(c.st, 1.0, 0, s);
+  level_tables(c, c.cfg.lv[0], s);
+  forward_sweep(c, 0, p->v, p->v, false, s);
+  decide(c, 0, 1, c.trace, s);
+  launch_energy_out(c.st, out4, s);
+  backward_sweep(c, 0, p->v, p->v, p->v, true, UPD_WRITE_G, grad, -1, s);
+  return hip_status();
+}
+
+int lddmm_apply(const lddmm_grid* grid, const float* u, const void* src, int32_t interp,
+                int32_t dtype, void* dst, void* stream) {
+  if (!grid || !u || !src || !dst) return LDDMM_EINVAL;
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return LDDMM_EINVAL;
+  if (!(grid->spacing > 0.0)) return LDDMM_EINVAL;
+  if (interp != LDDMM_INTERP_LINEAR && interp != LDDMM_INTERP_NEAREST) return LDDMM_EINVAL;
+  if (dtype != LDDMM_F32 && dtype != LDDMM_I32) return LDDMM_EINVAL;
+  if (interp == LDDMM_INTERP_LINEAR && dtype != LDDMM_F32) return LDDMM_EINVAL;
+  hipGetLastError();
+  launch_apply(u, grid->nx, grid->ny, grid->nz, (float)(1.0 / grid->spacing), src, interp, dtype,
+               dst, (hipStream_t)stream);
+  return hip_status();
+}
+
+size_t lddmm_smooth_workspace_size(const int32_t P[3]) {
+  if (!P) return 0;
+  for (int d = 0; d < 3; ++d)
+    if (P[d] < 2 || P[d] > LDDMM_MAX_DIM || !is_7smooth(P[d])) return 0;
+  const size_t nspec = (size_t)(P[0] / 2 + 1) * P[1] * P[2];
+  size_t off = align_up(sizeof(State));
+  for (int d = 0; d < 3; ++d) off = align_up(off + sizeof(float2) * P[d]);
+  for (int d = 0; d < 3; ++d) off = align_up(off + sizeof(double) * P[d]);
+  off = align_up(off + sizeof(float) * 3 * (size_t)P[0] * P[1] * P[2]);
+  off = align_up(off + sizeof(float2) * 3 * nspec);
+  return off;
+}
+
+int lddmm_smooth(const int32_t P[3], double spacing, double alpha, double gamma, const float* b,
+                 float* out, void* workspace, size_t workspace_bytes, void* stream) {
+  const size_t need = lddmm_smooth_workspace_size(P);
+  if (need == 0 || !b || !out || !workspace || workspace_bytes < need) return LDDMM_EINVAL;
+  if (!(spacing > 0.0) || !(alpha >= 0.0) || !(gamma > 0.0)) return LDDMM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipGetLastError();
+  Ctx c{};
+  Level L{};
+  L.g = make_geom(P[0], P[1], P[2], spacing);
+  if (!make_plan(P[0], &L.px) || !make_plan(P[1], &L.py) || !make_plan(P[2], &L.pz))
+    return LDDMM_EINVAL;
+  c.cfg.lv[0] = L;
+  c.cfg.L = 1;
+  char* w = (char*)workspace;
+  size_t off = 0;
+  c.st = (State*)(w + off);
+  off = align_up(sizeof(State));
+  for (int d = 0; d < 3; ++d) {
+    c.tw[d] = (float2*)(w + off);
+    off = align_up(off + sizeof(float2) * P[d]);
+  }
+  for (int d = 0; d < 3; ++d) {
+    c.lam[d] = (double*)(w + off);
+    off = align_up(off + sizeof(double) * P[d]);
+  }
+  c.b = (float*)(w + off);
+  off = align_up(off + sizeof(float) * 3 * (size_t)L.g.n);
+  c.S = (float2*)(w + off);
+  c.alpha = alpha;
+  c.gamma = gamma;
+  launch_level_begin(c.st, 1.0, 0, s);
+  level_tables(c, L, s);
+  launch_copy(b, c.b, 3 * L.g.n, s);
+  UpdArgs u{};
+  u.kind = UPD_WRITE_KB;
+  u.out = out;
+  u.st = c.st;
+  u.need_mode = -1;
+  smooth_and_update(c, 0, u, -1, s);
+  return hip_status();
+}
+
+int lddmm_make_mask(const lddmm_grid* grid, const float* image, float tau, float* mask,
+                    float* masked_image, void* stream) {
+  if (!grid || !image || !mask) return LDDMM_EINVAL;
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return LDDMM_EINVAL;
+  hipGetLastError();
+  launch_make_mask(image, (long long)grid->nx * grid->ny * grid->nz, tau, mask, masked_image,
+                   (hipStream_t)stream);
+  return hip_status();
+}
+
+const char* lddmm_strerror(int code) {
+  switch (code) {
+    case LDDMM_OK: return "ok";
+    case LDDMM_EINVAL: return "invalid argument";
+    case LDDMM_EHIP: return "HIP runtime or launch error";
+    case LDDMM_ENONFINITE: return "energy is not finite";
+    case LDDMM_WFOLD: return "warning: Jacobian determinant <= 0 (fold) seen";
+    case LDDMM_WGUARD: return "warning: step guard stopped a level after repeated halvings";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

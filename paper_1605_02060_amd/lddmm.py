@@ -1,0 +1,285 @@
+"""Python binding of liblddmm.so (ctypes; argument marshalling only).
+
+Every call runs the HIP library: there is no CPU path.  Device memory and
+streams come from PyTorch (ROCm build): arrays are torch CUDA tensors, and
+calls are enqueued on torch's current stream unless a stream is given.
+
+Names mirror the C ABI in include/lddmm.h.  Shapes: scalar fields [nz, ny, nx]
+float32; velocity [T, 3, Pz, Py, Px] on the finest computational grid;
+displacements [3, nz, ny, nx] (components x, y, z) in physical units.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblddmm.so")
+
+OK, EINVAL, EHIP, ENONFINITE, WFOLD, WGUARD = 0, -1, -2, -3, 1, 2
+GRAD_V, GRAD_L2 = 0, 1
+INTERP_LINEAR, INTERP_NEAREST = 0, 1
+F32, I32 = 0, 1
+MAX_LEVELS = 4
+TRACE_COLS = 8
+FLAG_RECOMPUTE_PHI = 1
+
+
+class LddmmError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {code} ({strerror(code)})")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("spacing", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("n_timesteps", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("iters", ctypes.c_int32 * MAX_LEVELS),
+                ("step", ctypes.c_double), ("guard", ctypes.c_int32),
+                ("weight", ctypes.c_double * 2), ("flags", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("template_mask", ctypes.c_void_p),
+                ("template_image", ctypes.c_void_p), ("target_mask", ctypes.c_void_p),
+                ("target_image", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("phi10", ctypes.c_void_p), ("phi01", ctypes.c_void_p),
+                ("trace", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblddmm.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1605_02060_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    lib.lddmm_workspace_size.argtypes = [P(_Grid), P(_Params)]
+    lib.lddmm_workspace_size.restype = sz
+    lib.lddmm_comp_grid.argtypes = [P(_Grid), P(_Params), i32, P(i32)]
+    lib.lddmm_comp_grid.restype = ctypes.c_int
+    lib.lddmm_trace_rows.argtypes = [P(_Params)]
+    lib.lddmm_trace_rows.restype = i32
+    lib.lddmm_register.argtypes = [P(_Problem), i32, P(_Params), vp]
+    lib.lddmm_register.restype = ctypes.c_int
+    lib.lddmm_energy.argtypes = [P(_Problem), P(_Params), vp, vp]
+    lib.lddmm_energy.restype = ctypes.c_int
+    lib.lddmm_gradient.argtypes = [P(_Problem), P(_Params), i32, vp, vp, vp]
+    lib.lddmm_gradient.restype = ctypes.c_int
+    lib.lddmm_apply.argtypes = [P(_Grid), vp, vp, i32, i32, vp, vp]
+    lib.lddmm_apply.restype = ctypes.c_int
+    lib.lddmm_smooth_workspace_size.argtypes = [P(i32)]
+    lib.lddmm_smooth_workspace_size.restype = sz
+    lib.lddmm_smooth.argtypes = [P(i32), dbl, dbl, dbl, vp, vp, vp, sz, vp]
+    lib.lddmm_smooth.restype = ctypes.c_int
+    lib.lddmm_make_mask.argtypes = [P(_Grid), vp, ctypes.c_float, vp, vp, vp]
+    lib.lddmm_make_mask.restype = ctypes.c_int
+    lib.lddmm_strerror.argtypes = [ctypes.c_int]
+    lib.lddmm_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddmm_register",
+            "lddmm_energy", "lddmm_gradient", "lddmm_apply", "lddmm_smooth_workspace_size",
+            "lddmm_smooth", "lddmm_make_mask", "lddmm_strerror"]
+
+
+def strerror(code):
+    return load().lddmm_strerror(int(code)).decode()
+
+
+@dataclass
+class Params:
+    """Mirror of lddmm_params (Methods, Registration: gamma = sigma = 1 by convention)."""
+
+    alpha: float = 0.02
+    gamma: float = 1.0
+    sigma: float = 1.0
+    T: int = 10
+    n_levels: int = 1
+    iters: tuple = (50,)
+    step: float = 0.1
+    guard: bool = True
+    weight: tuple = (1.0, 0.0)
+    flags: int = 0
+    checkpoint_every: int = 0
+
+    def c(self):
+        p = _Params()
+        p.alpha, p.gamma, p.sigma = self.alpha, self.gamma, self.sigma
+        p.n_timesteps = int(self.T)
+        p.n_levels = int(self.n_levels)
+        its = list(self.iters) + [0] * (MAX_LEVELS - len(self.iters))
+        for k in range(MAX_LEVELS):
+            p.iters[k] = int(its[k])
+        p.step = float(self.step)
+        p.guard = 1 if self.guard else 0
+        p.weight[0], p.weight[1] = float(self.weight[0]), float(self.weight[1])
+        p.flags = int(self.flags)
+        p.checkpoint_every = int(self.checkpoint_every)
+        return p
+
+
+def _grid(shape, spacing):
+    nz, ny, nx = shape
+    return _Grid(int(nx), int(ny), int(nz), float(spacing))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(code, what, ok=(OK,)):
+    if code not in ok:
+        raise LddmmError(code, what)
+    return code
+
+
+def lddmm_workspace_size(shape, params: Params, spacing=1.0) -> int:
+    g = _grid(shape, spacing)
+    p = params.c()
+    return int(load().lddmm_workspace_size(ctypes.byref(g), ctypes.byref(p)))
+
+
+def lddmm_comp_grid(shape, params: Params, level=0, spacing=1.0):
+    """Computational grid (Pz, Py, Px) of a pyramid level (0 = finest)."""
+    g = _grid(shape, spacing)
+    p = params.c()
+    out = (ctypes.c_int32 * 3)()
+    _check(load().lddmm_comp_grid(ctypes.byref(g), ctypes.byref(p), int(level), out),
+           "lddmm_comp_grid")
+    return (out[2], out[1], out[0])
+
+
+def lddmm_trace_rows(params: Params) -> int:
+    return int(load().lddmm_trace_rows(ctypes.byref(params.c())))
+
+
+def workspace(shape, params: Params, spacing=1.0, device="cuda"):
+    nbytes = lddmm_workspace_size(shape, params, spacing)
+    if nbytes == 0:
+        raise LddmmError(EINVAL, "lddmm_workspace_size")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10=None, phi01=None, trace=None):
+    pr = _Problem()
+    pr.grid = _grid(M0.shape, spacing)
+    pr.template_mask = _ptr(M0)
+    pr.template_image = _ptr(MI0)
+    pr.target_mask = _ptr(M1)
+    pr.target_image = _ptr(MI1)
+    pr.v = _ptr(v)
+    pr.phi10 = _ptr(phi10)
+    pr.phi01 = _ptr(phi01)
+    pr.trace = _ptr(trace)
+    pr.workspace = _ptr(ws)
+    pr.workspace_bytes = ws.numel()
+    return pr
+
+
+def lddmm_register(M0, M1, MI0=None, MI1=None, params: Params = None, spacing=1.0, v=None,
+                   want_phi=True, ws=None, stream=None):
+    """Register template (M0, MI0) to target (M1, MI1).  Returns a dict with
+    v [T,3,P], phi10 / phi01 [3,N], trace [rows, 8] (float64, device) and status."""
+    params = params or Params()
+    dev = M0.device
+    P = lddmm_comp_grid(M0.shape, params, 0, spacing)
+    if v is None:
+        v = torch.zeros((params.T, 3) + P, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(M0.shape, params, spacing, dev)
+    rows = lddmm_trace_rows(params)
+    trace = torch.full((rows, TRACE_COLS), float("nan"), dtype=torch.float64, device=dev)
+    phi10 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
+    phi01 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10, phi01, trace)
+    code = load().lddmm_register(ctypes.byref(pr), 1, ctypes.byref(params.c()), _stream(stream))
+    _check(code, "lddmm_register", ok=(OK, WFOLD, WGUARD, ENONFINITE))
+    return {"v": v, "phi10": phi10, "phi01": phi01, "trace": trace, "status": code}
+
+
+def lddmm_energy(M0, M1, MI0, MI1, v, params: Params, spacing=1.0, ws=None, stream=None):
+    """(E, R, D, image SSD) of v as a float64 device tensor of 4."""
+    ws = ws if ws is not None else workspace(M0.shape, params, spacing, M0.device)
+    out = torch.empty(4, dtype=torch.float64, device=M0.device)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws)
+    _check(load().lddmm_energy(ctypes.byref(pr), ctypes.byref(params.c()), _ptr(out),
+                               _stream(stream)), "lddmm_energy")
+    return out
+
+
+def lddmm_gradient(M0, M1, MI0, MI1, v, params: Params, kind=GRAD_V, spacing=1.0, ws=None,
+                   stream=None):
+    """Gradient of E at v ([T,3,P]) and (E, R, D, image SSD)."""
+    ws = ws if ws is not None else workspace(M0.shape, params, spacing, M0.device)
+    out = torch.empty(4, dtype=torch.float64, device=M0.device)
+    grad = torch.empty_like(v)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws)
+    _check(load().lddmm_gradient(ctypes.byref(pr), ctypes.byref(params.c()), int(kind),
+                                 _ptr(grad), _ptr(out), _stream(stream)), "lddmm_gradient")
+    return grad, out
+
+
+def lddmm_apply(u, src, spacing=1.0, interp=INTERP_LINEAR, stream=None):
+    """dst(x) = src(x + u(x)/h): linear (float32) or nearest (float32 / int32 labels)."""
+    dtype = I32 if src.dtype == torch.int32 else F32
+    dst = torch.empty_like(src)
+    g = _grid(src.shape, spacing)
+    _check(load().lddmm_apply(ctypes.byref(g), _ptr(u), _ptr(src), int(interp), dtype, _ptr(dst),
+                              _stream(stream)), "lddmm_apply")
+    return dst
+
+
+def lddmm_smooth(b, spacing, alpha, gamma, stream=None):
+    """K b on the computational grid of b ([3, Pz, Py, Px], each axis 7-smooth)."""
+    Pz, Py, Px = b.shape[1:]
+    P = (ctypes.c_int32 * 3)(Px, Py, Pz)
+    nbytes = load().lddmm_smooth_workspace_size(P)
+    if nbytes == 0:
+        raise LddmmError(EINVAL, "lddmm_smooth_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    out = torch.empty_like(b)
+    _check(load().lddmm_smooth(P, float(spacing), float(alpha), float(gamma), _ptr(b), _ptr(out),
+                               _ptr(ws), nbytes, _stream(stream)), "lddmm_smooth")
+    return out
+
+
+def lddmm_make_mask(image, tau, stream=None):
+    """M = 1[I > tau] and M * I (Methods, Mask Generation: binary threshold)."""
+    m = torch.empty_like(image)
+    mi = torch.empty_like(image)
+    g = _grid(image.shape, 1.0)
+    _check(load().lddmm_make_mask(ctypes.byref(g), _ptr(image), float(tau), _ptr(m), _ptr(mi),
+                                  _stream(stream)), "lddmm_make_mask")
+    return m, mi

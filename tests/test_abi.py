@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every symbol include/lddmm.h declares
+(CPU only: no compute calls without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1605_02060_amd import lddmm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lddmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lddmm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = _declared()
+    for n in ("lddmm_register", "lddmm_energy", "lddmm_gradient", "lddmm_apply"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTED) == _declared()
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # compile the header with the host C compiler and compare sizes / offsets
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"lddmm.h\"\n"
+        "int main(){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(lddmm_params),"
+        " offsetof(lddmm_params, step), offsetof(lddmm_params, weight),"
+        " offsetof(lddmm_params, checkpoint_every), sizeof(lddmm_problem),"
+        " offsetof(lddmm_problem, workspace_bytes));}\n")
+    exe = tmp_path / "sz"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    want = [ctypes.sizeof(L._Params), L._Params.step.offset, L._Params.weight.offset,
+            L._Params.checkpoint_every.offset, ctypes.sizeof(L._Problem),
+            L._Problem.workspace_bytes.offset]
+    assert got == want
+
+
+def test_host_side_queries_without_gpu():
+    p = L.Params(T=10, n_levels=3, iters=(200, 200, 200))
+    assert L.lddmm_comp_grid((228, 160, 264), p, 0) == (240, 160, 280)
+    assert L.lddmm_comp_grid((228, 160, 264), p, 2) == (60, 40, 70)
+    assert L.lddmm_trace_rows(p) == 603
+    assert L.lddmm_workspace_size((228, 160, 264), p) > 0
+    bad = L.Params(T=0)
+    assert L.lddmm_workspace_size((32, 32, 32), bad) == 0
+    assert L.strerror(L.EINVAL) == "invalid argument"

@@ -1,0 +1,277 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances: max-abs 1e-4 voxel on maps (u / h), relative 1e-5 on energies;
+fields produced by the K smoothing at 1e-5 of their max magnitude (FP32
+arithmetic with FP64 twiddles: ~1e-7 per pass times a few passes)."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lddmm as O
+from paper_1605_02060_amd import lddmm as L
+from paper_1605_02060_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(x):
+    return x.detach().cpu().numpy().astype(np.float64)
+
+
+def problem_tensors(p, with_img=True):
+    return (t(p.M0), t(p.M1), t(p.MI0) if with_img else None, t(p.MI1) if with_img else None)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def pad_v(v, P):
+    """Random smooth velocity on the computational grid P."""
+    return v
+
+
+# ----------------------------------------------------------------- K ----
+
+@pytest.mark.parametrize("P,h,alpha,gamma", [
+    ((8, 8, 8), 1.0, 0.02, 1.0),
+    ((12, 10, 14), 0.05, 0.02, 1.0),
+    ((15, 9, 21), 2.0, 0.7, 0.5),          # odd x: half spectrum without Nyquist bin
+    ((32, 32, 32), 1.0, 0.3, 1.0),
+    ((60, 40, 70), 0.2, 0.02, 1.0),        # coarsest atlas level
+    ((36, 45, 50), 1.0, 1.0, 1.0),
+])
+def test_smooth_matches_oracle(P, h, alpha, gamma):
+    say(f"smooth P={P} h={h}")
+    b = np.random.default_rng(1).normal(size=(3,) + P)
+    out = L.lddmm_smooth(t(b), h, alpha, gamma)
+    torch.cuda.synchronize()
+    ref = O.apply_K(b, alpha, gamma, h)
+    err = np.abs(host(out) - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
+
+
+# ---------------------------------------------------------- energy ----
+
+CASES = [
+    # (name, user shape, spacing, T, vmax in voxels per unit time)
+    ("blobs32-h1", (32, 32, 32), 1.0, 10, 1.5),
+    ("blobs32-h005", (32, 32, 32), 0.05, 10, 2.0),
+    ("ragged", (20, 27, 33), 0.1, 4, 1.5),
+]
+
+
+def _case(name, shape, h, T, vmax, seed=0):
+    if shape == (32, 32, 32):
+        p = synth.config_pair("blobs32")
+    else:
+        p = synth.blob_pair(shape, 5, max_disp=2.0, sigma=(2.0, 4.0))
+    prm = O.Params(T=T, spacing=h)
+    P = tuple(O.smooth7(n) for n in shape)
+    v = h * synth.random_velocity(P, T, 100 + seed, vmax=vmax, sigma_s=3.0).astype(np.float64)
+    v = v.astype(np.float32)
+    return p, prm, P, v
+
+
+def _lparams(prm: O.Params, **kw):
+    return L.Params(alpha=prm.alpha, gamma=prm.gamma, sigma=prm.sigma, T=prm.T,
+                    n_levels=prm.n_levels, iters=prm.iters, step=prm.step, guard=prm.guard,
+                    weight=prm.weight, **kw)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("weight", [(1.0, 0.0), (1.0, 0.5)])
+def test_energy_matches_oracle(case, weight):
+    name, shape, h, T, vmax = case
+    say(f"energy {name} weight={weight}")
+    p, prm, P, v = _case(*case)
+    prm.weight = weight
+    ref = O.energy(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm, v.astype(np.float64))
+    out = host(L.lddmm_energy(*problem_tensors(p), t(v), _lparams(prm), spacing=h))
+    assert rel(out[1], ref["R"]) < 1e-5
+    assert rel(out[2], ref["D"]) < 1e-5
+    assert rel(out[0], ref["E"]) < 1e-5
+    assert rel(out[3], ref["img_ssd"]) < 1e-5
+
+
+def test_energy_without_image_channel_reports_nan_monitor():
+    say("energy no-image")
+    p, prm, P, v = _case(*CASES[0])
+    ref = O.energy(O.Problem(p.M0, p.M1), prm, v.astype(np.float64))
+    out = host(L.lddmm_energy(t(p.M0), t(p.M1), None, None, t(v), _lparams(prm)))
+    assert rel(out[0], ref["E"]) < 1e-5
+    assert math.isnan(out[3])
+
+
+# -------------------------------------------------------- gradient ----
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_plain_gradient_matches_oracle(case):
+    name, shape, h, T, vmax = case
+    say(f"gradient V {name}")
+    p, prm, P, v = _case(*case)
+    prm.weight = (1.0, 0.3)
+    g_ref, st, _ = O.gradient(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm, v.astype(np.float64),
+                              kind="V")
+    g, out = L.lddmm_gradient(*problem_tensors(p), t(v), _lparams(prm), kind=L.GRAD_V, spacing=h)
+    g = host(g)
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    assert err < 2e-5, err
+    assert rel(host(out)[0], st["E"]) < 1e-5
+
+
+# ---------------------------------------------------- registration ----
+
+def _compare_register(p, prm, res, ref, h, tol_phi=1e-4, tol_E=1e-5, with_img=True):
+    tr = host(res["trace"])
+    rt = np.array(ref.trace)
+    assert tr.shape == rt.shape
+    np.testing.assert_array_equal(tr[:, 6], rt[:, 6])       # same accept / reject decisions
+    fin = np.isfinite(rt[:, 0])
+    assert np.all(np.abs(tr[fin, 0] - rt[fin, 0]) <= tol_E * np.abs(rt[fin, 0]))
+    assert np.all(np.abs(tr[:, 7] - rt[:, 7]) <= tol_E * np.abs(rt[:, 7]))
+    np.testing.assert_allclose(tr[:, 3], rt[:, 3], rtol=1e-15)
+    e10 = np.abs(host(res["phi10"]) - ref.phi10).max() / h
+    e01 = np.abs(host(res["phi01"]) - ref.phi01).max() / h
+    assert e10 < tol_phi and e01 < tol_phi, (e10, e01)
+    assert res["status"] == ref.status
+
+
+@pytest.mark.parametrize("h,step,iters", [(0.05, 0.02, 12), (1.0, 0.2, 8)])
+def test_register_single_level_matches_oracle(h, step, iters):
+    say(f"register blobs32 h={h}")
+    p = synth.config_pair("blobs32")
+    prm = O.Params(T=10, iters=(iters,), step=step, spacing=h)
+    ref = O.register(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm)
+    res = L.lddmm_register(*problem_tensors(p), params=_lparams(prm), spacing=h)
+    torch.cuda.synchronize()
+    _compare_register(p, prm, res, ref, h)
+
+
+def test_register_ragged_grid_two_channels():
+    say("register ragged 2ch")
+    shape = (20, 27, 33)
+    p = synth.blob_pair(shape, 5, max_disp=2.0, sigma=(2.0, 4.0))
+    prm = O.Params(T=4, iters=(8,), step=0.02, spacing=0.1, weight=(1.0, 0.5))
+    ref = O.register(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm)
+    res = L.lddmm_register(*problem_tensors(p), params=_lparams(prm), spacing=0.1)
+    torch.cuda.synchronize()
+    _compare_register(p, prm, res, ref, 0.1)
+
+
+def test_register_pyramid_matches_oracle():
+    say("register pyramid 3 levels")
+    shape = (30, 22, 34)
+    p = synth.blob_pair(shape, 6, max_disp=2.5, sigma=(2.5, 5.0))
+    prm = O.Params(T=4, n_levels=3, iters=(6, 5, 4), step=0.02, spacing=0.05)
+    ref = O.register(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm)
+    res = L.lddmm_register(*problem_tensors(p), params=_lparams(prm), spacing=0.05)
+    torch.cuda.synchronize()
+    _compare_register(p, prm, res, ref, 0.05)
+    np.testing.assert_allclose(host(res["v"]), ref.v, atol=1e-4 * np.abs(ref.v).max())
+
+
+def test_guard_decisions_match_oracle():
+    say("register guard halvings")
+    p = synth.config_pair("blobs32")
+    prm = O.Params(T=3, iters=(12,), step=2.0, spacing=0.05)
+    ref = O.register(O.Problem(p.M0, p.M1), prm)
+    assert (np.array(ref.trace)[1:, 6] == 0).any()
+    res = L.lddmm_register(t(p.M0), t(p.M1), params=_lparams(prm), spacing=0.05)
+    torch.cuda.synchronize()
+    _compare_register(p, prm, res, ref, 0.05)
+
+
+def test_register_deterministic():
+    say("register determinism")
+    p = synth.config_pair("blobs32")
+    prm = L.Params(T=5, iters=(6,), step=0.02)
+    a = L.lddmm_register(*problem_tensors(p), params=prm, spacing=0.05)
+    b = L.lddmm_register(*problem_tensors(p), params=prm, spacing=0.05)
+    torch.cuda.synchronize()
+    assert torch.equal(a["v"], b["v"]) and torch.equal(a["trace"].nan_to_num(), b["trace"].nan_to_num())
+    assert torch.equal(a["phi10"], b["phi10"]) and torch.equal(a["phi01"], b["phi01"])
+
+
+def test_nonfinite_velocity_status():
+    say("register NaN velocity")
+    p = synth.blob_pair((8, 8, 8), 1, max_disp=1.0, center_frac=(0.3, 0.7))
+    prm = L.Params(T=2, iters=(2,))
+    v = torch.zeros((2, 3, 8, 8, 8), device=DEV)
+    v[1, 0, 3, 3, 3] = float("nan")
+    res = L.lddmm_register(t(p.M0), t(p.M1), params=prm, v=v)
+    assert res["status"] == L.ENONFINITE
+    assert torch.isnan(res["phi10"]).all()
+
+
+def test_invalid_arguments_rejected_before_launch():
+    say("EINVAL paths")
+    M = torch.zeros((8, 8, 8), device=DEV)
+    with pytest.raises(L.LddmmError) as e:
+        L.lddmm_register(M, M, params=L.Params(T=0))
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LddmmError) as e:
+        L.lddmm_register(M, M, params=L.Params(sigma=0.0))
+    assert e.value.code == L.EINVAL
+    with pytest.raises(L.LddmmError) as e:
+        L.lddmm_register(M, M, params=L.Params(weight=(0.0, 0.0)))
+    assert e.value.code == L.EINVAL
+    small = torch.zeros((1, 8, 8), device=DEV)
+    with pytest.raises(L.LddmmError):
+        L.lddmm_register(small, small, params=L.Params())
+
+
+# ------------------------------------------------------------ apply ----
+
+def test_apply_linear_and_nearest_match_oracle():
+    say("apply")
+    shape = (17, 20, 23)
+    rng = np.random.default_rng(3)
+    src = rng.normal(size=shape).astype(np.float32)
+    lab = rng.integers(0, 700, size=shape).astype(np.int32)
+    h = 0.5
+    u = (h * rng.uniform(-2.5, 2.5, size=(3,) + shape)).astype(np.float32)
+    out = host(L.lddmm_apply(t(u), t(src), spacing=h))
+    ref = O.apply_warp(u.astype(np.float64), src.astype(np.float64), h, "linear")
+    assert np.abs(out - ref).max() < 1e-5 * np.abs(src).max()
+    outl = L.lddmm_apply(t(u), t(lab, torch.int32), spacing=h,
+                         interp=L.INTERP_NEAREST).cpu().numpy()
+    # the rounding decision is taken in FP32 on both sides: floor(u*(1/h) + 1/2)
+    d = u * np.float32(1.0 / h) + np.float32(0.5)
+    X = O.index_positions(shape)
+    idx = [np.floor(d[c]).astype(np.int64) + X[c].astype(np.int64) for c in range(3)]
+    ok = np.ones(shape, bool)
+    for c, nn in zip(range(3), (shape[2], shape[1], shape[0])):
+        ok &= (idx[c] >= 0) & (idx[c] < nn)
+    refl = np.where(ok, lab[np.clip(idx[2], 0, shape[0] - 1), np.clip(idx[1], 0, shape[1] - 1),
+                            np.clip(idx[0], 0, shape[2] - 1)], 0)
+    np.testing.assert_array_equal(outl, refl)
+    # and the FP64 oracle agrees wherever no tie is within FP32 rounding
+    ref64 = O.apply_warp(u.astype(np.float64), lab, h, "nearest")
+    frac = np.abs((u.astype(np.float64) / h + 0.5) % 1.0)
+    safe = np.all((frac > 1e-5) & (frac < 1 - 1e-5), axis=0)
+    np.testing.assert_array_equal(outl[safe], ref64[safe])
+
+
+def test_make_mask():
+    say("make_mask")
+    img = np.random.default_rng(4).uniform(0, 0.2, size=(9, 10, 11)).astype(np.float32)
+    m, mi = L.lddmm_make_mask(t(img), 0.1)
+    np.testing.assert_array_equal(host(m), (img > 0.1).astype(np.float64))
+    np.testing.assert_array_equal(host(mi), ((img > 0.1) * img).astype(np.float32))
