@@ -171,6 +171,37 @@ int lddmm_smooth(const int32_t P[3], double spacing, double alpha, double gamma,
 int lddmm_make_mask(const lddmm_grid *grid, const float *image, float tau, float *mask,
                     float *masked_image, void *stream);
 
+/*
+ * Kernel-class timing with HIP events recorded on the launch stream around each
+ * launch of the selected classes (bit k of class_mask = class k below) whose
+ * grid has at least min_voxels voxels.
+ * lddmm_profile_begin clears the record and starts recording for every later
+ * call of this process; lddmm_profile_end synchronises the recorded events,
+ * writes per class the summed duration (ms), the number of launches and the
+ * number of grid voxels those launches covered (arrays of LDDMM_PROF_CLASSES,
+ * host memory, may be NULL) and stops recording.  Not thread-safe.
+ */
+#define LDDMM_PROF_FORWARD   0   /* forward map step + template warp + energy partials */
+#define LDDMM_PROF_BACKWARD  1   /* backward map step + Jacobian + body force */
+#define LDDMM_PROF_FFT_X     2   /* x forward pass of K (real -> half spectrum) */
+#define LDDMM_PROF_FFT_Y     3   /* y forward pass */
+#define LDDMM_PROF_FFT_ZK    4   /* z pass: forward, K_hat, inverse */
+#define LDDMM_PROF_FFT_YINV  5   /* y inverse pass */
+#define LDDMM_PROF_FFT_XINV  6   /* x inverse pass + velocity update */
+#define LDDMM_PROF_OTHER     7   /* retry, guard decision, pyramid, setup */
+#define LDDMM_PROF_CLASSES   8
+int lddmm_profile_begin(uint32_t class_mask, int64_t min_voxels);
+int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
+
+/*
+ * Launch-shape tunables (process-wide; results are identical for every value,
+ * only speed changes).  LDDMM_TUNE_SWEEP_BLOCKS: blocks of the forward and
+ * backward sweep kernels (rounded to a multiple of 8, clamped to [8, 4096];
+ * default 2048).  Returns LDDMM_OK or LDDMM_EINVAL.
+ */
+#define LDDMM_TUNE_SWEEP_BLOCKS 0
+int lddmm_set_tunable(int32_t which, int32_t value);
+
 /* Human-readable text of a status code (static storage). */
 const char *lddmm_strerror(int code);
 

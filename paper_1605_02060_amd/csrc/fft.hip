@@ -2,7 +2,9 @@
 // as a 3D DFT on the computational grid: mixed-radix (2,3,4,5,7,8) Stockham
 // transforms staged in LDS, one axis per pass.
 //
-//   pass x-fwd : real body force b [3][P] -> half spectrum S [3][nz][ny][hx]
+//   pass x-fwd : real body force b [3][P] -> half spectrum S [3][nz][ny][hs]
+//                (hx = nx/2 + 1 used entries per row, rows padded to hs, a
+//                multiple of 16 entries, so 128-byte tile segments stay aligned)
 //                (two real lines packed into one complex transform)
 //   pass y     : transform along y, in place on S
 //   pass z+K   : transform along z, multiply by K_hat / |P|, inverse along z
@@ -32,11 +34,15 @@ bool make_plan(int n, FFTPlan* p) {
     p->radix[st++] = r;
     return true;
   };
-  while (p2 >= 3) {
+  // powers of two: radix 8 where possible, two radix-4 stages instead of 8 x 2
+  while (p2 >= 3 && p2 != 4) {
     if (!push(8)) return false;
     p2 -= 3;
   }
-  if (p2 == 2 && !push(4)) return false;
+  while (p2 >= 2) {
+    if (!push(4)) return false;
+    p2 -= 2;
+  }
   if (p2 == 1 && !push(2)) return false;
   for (int r : {3, 5, 7}) {
     while (m % r == 0) {
@@ -45,6 +51,12 @@ bool make_plan(int n, FFTPlan* p) {
     }
   }
   p->nst = st;
+  int ns = 1;
+  for (int k = 0; k < st; ++k) {
+    p->fnb[k] = make_fastdiv((uint32_t)(n / p->radix[k]));
+    p->fns[k] = make_fastdiv((uint32_t)ns);
+    ns *= p->radix[k];
+  }
   return m == 1;
 }
 
@@ -122,6 +134,100 @@ struct Roots<8> {
                                  0.f, -0.70710678118654752f, -1.f, -0.70710678118654752f};
 };
 
+// (a) * (-i)
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+template <int R>
+__device__ __forceinline__ void radix_dft(float2 (&v)[R]);
+
+template <>
+__device__ __forceinline__ void radix_dft<2>(float2 (&v)[2]) {
+  const float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+// 4-point DFT: W4 = -i.
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 t0 = cadd(x0, x2), t1 = csub(x0, x2);
+  const float2 t2 = cadd(x1, x3), t3 = mul_mi(csub(x1, x3));
+  x0 = cadd(t0, t2);
+  x2 = csub(t0, t2);
+  x1 = cadd(t1, t3);
+  x3 = csub(t1, t3);
+}
+
+template <>
+__device__ __forceinline__ void radix_dft<4>(float2 (&v)[4]) {
+  dft4(v[0], v[1], v[2], v[3]);
+}
+
+// 8-point DFT as two 4-point DFTs (even / odd samples) and W8^k twiddles.
+template <>
+__device__ __forceinline__ void radix_dft<8>(float2 (&v)[8]) {
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  const float r = 0.70710678118654752f;
+  // W8^1 = (1 - i)/sqrt2, W8^2 = -i, W8^3 = -(1 + i)/sqrt2
+  const float2 w1 = make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
+  const float2 w2 = mul_mi(o2);
+  const float2 w3 = make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, w1);
+  v[5] = csub(e1, w1);
+  v[2] = cadd(e2, w2);
+  v[6] = csub(e2, w2);
+  v[3] = cadd(e3, w3);
+  v[7] = csub(e3, w3);
+}
+
+// Odd R: pair x[p] with x[R-p].  With a_p = x_p + x_{R-p}, b_p = x_p - x_{R-p}:
+//   y_m     = x_0 + sum_p a_p cos(2 pi p m / R) - i sum_p b_p sin(2 pi p m / R)
+//   y_{R-m} = x_0 + sum_p a_p cos(2 pi p m / R) + i sum_p b_p sin(2 pi p m / R)
+template <int R>
+__device__ __forceinline__ void radix_dft_odd(float2 (&v)[R]) {
+  constexpr int H = (R - 1) / 2;
+  float2 a[H], b[H];
+#pragma unroll
+  for (int p = 1; p <= H; ++p) {
+    a[p - 1] = cadd(v[p], v[R - p]);
+    b[p - 1] = csub(v[p], v[R - p]);
+  }
+  const float2 x0 = v[0];
+  float2 y0 = x0;
+#pragma unroll
+  for (int p = 0; p < H; ++p) y0 = cadd(y0, a[p]);
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    float cr = x0.x, ci = x0.y, sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int p = 1; p <= H; ++p) {
+      const int k = (p * m) % R;
+      const float c = Roots<R>::c[k], s = Roots<R>::s[k];
+      cr += a[p - 1].x * c;
+      ci += a[p - 1].y * c;
+      sr += b[p - 1].x * s;
+      si += b[p - 1].y * s;
+    }
+    // -i * (sr + i si) = si - i sr
+    v[m] = make_float2(cr + si, ci - sr);
+    v[R - m] = make_float2(cr - si, ci + sr);
+  }
+  v[0] = y0;
+}
+
+template <>
+__device__ __forceinline__ void radix_dft<3>(float2 (&v)[3]) { radix_dft_odd<3>(v); }
+template <>
+__device__ __forceinline__ void radix_dft<5>(float2 (&v)[5]) { radix_dft_odd<5>(v); }
+template <>
+__device__ __forceinline__ void radix_dft<7>(float2 (&v)[7]) { radix_dft_odd<7>(v); }
+
 template <int R>
 __device__ __forceinline__ void radix_dft(float2 (&v)[R]) {
   float2 out[R];
@@ -141,15 +247,18 @@ __device__ __forceinline__ void radix_dft(float2 (&v)[R]) {
   for (int m = 0; m < R; ++m) v[m] = out[m];
 }
 
-// One Stockham stage on nl lines of length N held in LDS (line l at sm + l*N).
-// Ns = product of the radices already applied.  All reads of the stage happen
-// before the barrier and all writes after it, so the stage runs in place.
-template <int R>
-__device__ __forceinline__ void fft_stage(float2* sm, int N, int nl, int Ns,
+// One Stockham stage on nl lines of length N held in LDS (line l at sm + l*ls).
+// Ns = product of the radices already applied.  All reads of the stage (and its
+// twiddles) happen before the barrier and all writes after it, so the stage
+// runs in place.
+template <int R, int EMAX>
+__device__ __forceinline__ void fft_stage(float2* sm, int N, int ls, int nl, int Ns,
+                                          const FastDiv& fnb, const FastDiv& fns,
                                           const float2* __restrict__ tw) {
-  constexpr int NB = (kEMax + R - 1) / R;
+  constexpr int NB = (EMAX + R - 1) / R;
   const int nb = N / R;
   const int total = nl * nb;
+  const int step = N / (Ns * R);
   float2 val[NB][R];
   int line[NB], jj[NB];
 #pragma unroll
@@ -158,26 +267,29 @@ __device__ __forceinline__ void fft_stage(float2* sm, int N, int nl, int Ns,
     line[t] = -1;
     jj[t] = 0;
     if (bi < total) {
-      const int l = bi / nb;
+      const int l = (int)fdiv((uint32_t)bi, fnb);
       const int j = bi - l * nb;
       line[t] = l;
       jj[t] = j;
-      const float2* src = sm + l * N + j;
+      const float2* src = sm + l * ls + j;
 #pragma unroll
       for (int q = 0; q < R; ++q) val[t][q] = src[q * nb];
+      if (Ns > 1) {
+        const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
+#pragma unroll
+        for (int q = 1; q < R; ++q) val[t][q] = cmul(val[t][q], tw[q * k * step]);
+      }
     }
   }
   __syncthreads();
-  const int step = N / (Ns * R);
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     if (line[t] >= 0) {
       const int j = jj[t];
-      const int k = j % Ns;
-#pragma unroll
-      for (int q = 1; q < R; ++q) val[t][q] = cmul(val[t][q], tw[q * k * step]);
+      const int jq = (int)fdiv((uint32_t)j, fns);
+      const int k = j - jq * Ns;
       radix_dft<R>(val[t]);
-      float2* dst = sm + line[t] * N + (j / Ns) * Ns * R + k;
+      float2* dst = sm + line[t] * ls + jq * Ns * R + k;
 #pragma unroll
       for (int q = 0; q < R; ++q) dst[q * Ns] = val[t][q];
     }
@@ -185,18 +297,21 @@ __device__ __forceinline__ void fft_stage(float2* sm, int N, int nl, int Ns,
   __syncthreads();
 }
 
-// Forward DFT of nl lines of length p.n in LDS (natural order in and out).
-__device__ __forceinline__ void lds_fft(float2* sm, int nl, const FFTPlan& p, const float2* __restrict__ tw) {
+// Forward DFT of nl lines of length p.n in LDS (line stride ls; natural order in and out).
+// Requires nl * p.n <= 256 * EMAX (each thread holds at most EMAX values per stage).
+template <int EMAX>
+__device__ __forceinline__ void lds_fft(float2* sm, int ls, int nl, const FFTPlan& p,
+                                        const float2* __restrict__ tw) {
   int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.radix[s];
     switch (R) {
-      case 2: fft_stage<2>(sm, p.n, nl, Ns, tw); break;
-      case 3: fft_stage<3>(sm, p.n, nl, Ns, tw); break;
-      case 4: fft_stage<4>(sm, p.n, nl, Ns, tw); break;
-      case 5: fft_stage<5>(sm, p.n, nl, Ns, tw); break;
-      case 7: fft_stage<7>(sm, p.n, nl, Ns, tw); break;
-      default: fft_stage<8>(sm, p.n, nl, Ns, tw); break;
+      case 2: fft_stage<2, EMAX>(sm, p.n, ls, nl, Ns, p.fnb[s], p.fns[s], tw); break;
+      case 3: fft_stage<3, EMAX>(sm, p.n, ls, nl, Ns, p.fnb[s], p.fns[s], tw); break;
+      case 4: fft_stage<4, EMAX>(sm, p.n, ls, nl, Ns, p.fnb[s], p.fns[s], tw); break;
+      case 5: fft_stage<5, EMAX>(sm, p.n, ls, nl, Ns, p.fnb[s], p.fns[s], tw); break;
+      case 7: fft_stage<7, EMAX>(sm, p.n, ls, nl, Ns, p.fnb[s], p.fns[s], tw); break;
+      default: fft_stage<8, EMAX>(sm, p.n, ls, nl, Ns, p.fnb[s], p.fns[s], tw); break;
     }
     Ns *= R;
   }
@@ -206,11 +321,16 @@ __device__ __forceinline__ bool gate(const State* st, int need_mode) {
   return need_mode < 0 || st->mode == need_mode;
 }
 
+// Tile geometry of one FFT block: `nl` lines of length N, line stride `ls` in LDS.
+// Every thread moves at most EMAX elements between HBM and LDS; all of its global
+// loads are issued before any LDS write so their latencies overlap.
+
 // ----------------------------------------------------------- x forward ----
 // Row rho = z*ny + y.  Rows are processed in pairs (2m, 2m+1): complex lines
 //   Z0 = bx[2m] + i by[2m],  Z1 = bx[2m+1] + i by[2m+1],  Z2 = bz[2m] + i bz[2m+1].
 // After the DFT, for k < hx:  A[k] = (Z[k] + conj Z[-k]) / 2,  B[k] = (Z[k] - conj Z[-k]) / 2i.
 
+template <int EMAX>
 __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(const float* __restrict__ b,
                                                       float2* __restrict__ S, Geom g, FFTPlan p,
                                                       const float2* __restrict__ tw, int ppb,
@@ -222,27 +342,38 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(const float* __restrict__ 
   const int nrows = g.ny * g.nz;
   const int pair0 = blockIdx.x * ppb;
   const int nl = 3 * ppb;
-  for (int e = threadIdx.x; e < nl * N; e += kBlock) {
-    const int l = e / N, x = e - l * N;
-    const int pp = l / 3, which = l - 3 * pp;
-    const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
+  const int tot = nl * N;
+  float2 tmp[EMAX];
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const int e = threadIdx.x + r * kBlock;
     float2 z = make_float2(0.f, 0.f);
-    if (which == 0) {
-      if (r0 < nrows) z = make_float2(b[(long long)r0 * N + x], b[n + (long long)r0 * N + x]);
-    } else if (which == 1) {
-      if (r1 < nrows) z = make_float2(b[(long long)r1 * N + x], b[n + (long long)r1 * N + x]);
-    } else {
-      const float re = r0 < nrows ? b[2 * n + (long long)r0 * N + x] : 0.f;
-      const float im = r1 < nrows ? b[2 * n + (long long)r1 * N + x] : 0.f;
-      z = make_float2(re, im);
+    if (e < tot) {
+      const int l = (int)fdiv((uint32_t)e, g.fx), x = e - l * N;
+      const int pp = l / 3, which = l - 3 * pp;
+      const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
+      if (which == 0) {
+        if (r0 < nrows) z = make_float2(b[(long long)r0 * N + x], b[n + (long long)r0 * N + x]);
+      } else if (which == 1) {
+        if (r1 < nrows) z = make_float2(b[(long long)r1 * N + x], b[n + (long long)r1 * N + x]);
+      } else {
+        const float re = r0 < nrows ? b[2 * n + (long long)r0 * N + x] : 0.f;
+        const float im = r1 < nrows ? b[2 * n + (long long)r1 * N + x] : 0.f;
+        z = make_float2(re, im);
+      }
     }
-    sm[e] = z;
+    tmp[r] = z;
+  }
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const int e = threadIdx.x + r * kBlock;
+    if (e < tot) sm[e] = tmp[r];
   }
   __syncthreads();
-  lds_fft(sm, nl, p, tw);
-  const int hx = g.hx;
+  lds_fft<EMAX>(sm, N, nl, p, tw);
+  const int hx = g.hx, hs = g.hs;
   for (int e = threadIdx.x; e < nl * hx; e += kBlock) {
-    const int l = e / hx, k = e - l * hx;
+    const int l = (int)fdiv((uint32_t)e, g.fhx), k = e - l * hx;
     const int pp = l / 3, which = l - 3 * pp;
     const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
     const float2 zk = sm[l * N + k];
@@ -252,131 +383,191 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(const float* __restrict__ 
     const float2 B = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));
     if (which == 0) {
       if (r0 < nrows) {
-        S[(long long)r0 * hx + k] = A;
-        S[g.nspec + (long long)r0 * hx + k] = B;
+        S[(long long)r0 * hs + k] = A;
+        S[g.nspec + (long long)r0 * hs + k] = B;
       }
     } else if (which == 1) {
       if (r1 < nrows) {
-        S[(long long)r1 * hx + k] = A;
-        S[g.nspec + (long long)r1 * hx + k] = B;
+        S[(long long)r1 * hs + k] = A;
+        S[g.nspec + (long long)r1 * hs + k] = B;
       }
     } else {
-      if (r0 < nrows) S[2 * g.nspec + (long long)r0 * hx + k] = A;
-      if (r1 < nrows) S[2 * g.nspec + (long long)r1 * hx + k] = B;
+      if (r0 < nrows) S[2 * g.nspec + (long long)r0 * hs + k] = A;
+      if (r1 < nrows) S[2 * g.nspec + (long long)r1 * hs + k] = B;
     }
   }
 }
 
-static int pairs_per_block(int N) {
+// Row pairs per block of the x passes and the register budget they need.
+static int pairs_per_block(int N, int* emax) {
   int ppb = kFFTElems / (3 * N);
   if (ppb < 1) ppb = 1;
   if (ppb > 8) ppb = 8;
+  const int tot = 3 * ppb * N;
+  *emax = tot <= kBlock * 8 ? 8 : (tot <= kBlock * 16 ? 16 : 32);
   return ppb;
 }
 
 void launch_fft_x_fwd(const float* b, float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
                       const State* st, int need_mode, hipStream_t s) {
-  const int ppb = pairs_per_block(g.nx);
+  int emax;
+  const int ppb = pairs_per_block(g.nx, &emax);
   const int npairs = (g.ny * g.nz + 1) / 2;
   const int grid = (npairs + ppb - 1) / ppb;
   const size_t lds = (size_t)3 * ppb * g.nx * sizeof(float2);
-  hipLaunchKernelGGL(k_fft_x_fwd, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb, st,
-                     need_mode);
+  if (emax == 8)
+    hipLaunchKernelGGL(k_fft_x_fwd<8>, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb, st,
+                       need_mode);
+  else if (emax == 16)
+    hipLaunchKernelGGL(k_fft_x_fwd<16>, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb,
+                       st, need_mode);
+  else
+    hipLaunchKernelGGL(k_fft_x_fwd<32>, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb,
+                       st, need_mode);
 }
 
-// -------------------------------------------------------------- y pass ----
-// Tile: TX consecutive kx of one (component, z) slab, all ny rows.
+// ------------------------------------------------------ y and z passes ----
+// Tile: TX consecutive kx of one (component, slab), all N points along the
+// transform axis; line c of the tile is the column kx0 + c (LDS stride N + 1,
+// so the transposing writes spread over the banks).
 
-static int tile_cols(int N) {
-  int tx = 32;
-  while (tx > 1 && tx * N > kFFTElems) tx >>= 1;
+static int ilog2(int v) {
+  int k = 0;
+  while ((1 << (k + 1)) <= v) ++k;
+  return k;
+}
+
+static int tile_cols(int N, int* emax) {
+  int tx = 16;
+  while (tx > 2 && tx * N > 2 * kFFTElems) tx >>= 1;
+  const int tot = tx * N;
+  *emax = tot <= kBlock * 8 ? 8 : (tot <= kBlock * 16 ? 16 : 32);
   return tx;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fft_y(float2* __restrict__ S, Geom g, FFTPlan p,
-                                                  const float2* __restrict__ tw, int TX,
-                                                  int inverse, const State* st, int need_mode) {
-  if (!gate(st, need_mode)) return;
-  extern __shared__ float2 sm[];
-  const int N = g.ny, hx = g.hx;
-  const int kx0 = blockIdx.x * TX;
-  float2* base = S + (long long)blockIdx.z * g.nspec + (long long)blockIdx.y * g.ny * hx;
-  for (int e = threadIdx.x; e < TX * N; e += kBlock) {
-    const int c = e % TX, y = e / TX;
+template <int EMAX, bool INV>
+__device__ __forceinline__ void tile_load(float2* sm, const float2* __restrict__ base, int lgTX,
+                                          int N, int ls, int hx, int kx0, int stride) {
+  float2 tmp[EMAX];
+  const int TX = 1 << lgTX;
+  const int tot = TX * N;
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const int e = threadIdx.x + r * kBlock;
     float2 v = make_float2(0.f, 0.f);
-    if (kx0 + c < hx) v = base[(long long)y * hx + kx0 + c];
-    if (inverse) v = cconj(v);
-    sm[c * N + y] = v;
+    if (e < tot) {
+      const int c = e & (TX - 1), y = e >> lgTX;
+      if (kx0 + c < hx) v = base[y * stride + kx0 + c];
+    }
+    tmp[r] = INV ? cconj(v) : v;
+  }
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const int e = threadIdx.x + r * kBlock;
+    if (e < tot) {
+      const int c = e & (TX - 1), y = e >> lgTX;
+      sm[c * ls + y] = tmp[r];
+    }
   }
   __syncthreads();
-  lds_fft(sm, TX, p, tw);
+}
+
+template <bool INV>
+__device__ __forceinline__ void tile_store(const float2* sm, float2* __restrict__ base, int lgTX,
+                                           int N, int ls, int hx, int kx0, int stride) {
+  const int TX = 1 << lgTX;
   for (int e = threadIdx.x; e < TX * N; e += kBlock) {
-    const int c = e % TX, y = e / TX;
+    const int c = e & (TX - 1), y = e >> lgTX;
     if (kx0 + c < hx) {
-      float2 v = sm[c * N + y];
-      if (inverse) v = cconj(v);
-      base[(long long)y * hx + kx0 + c] = v;
+      const float2 v = sm[c * ls + y];
+      base[y * stride + kx0 + c] = INV ? cconj(v) : v;
     }
   }
 }
 
-void launch_fft_y(float2* S, const Geom& g, const FFTPlan& p, const float2* tw, int inverse,
-                  const State* st, int need_mode, hipStream_t s) {
-  const int TX = tile_cols(g.ny);
-  dim3 grid((g.hx + TX - 1) / TX, g.nz, 3);
-  const size_t lds = (size_t)TX * g.ny * sizeof(float2);
-  hipLaunchKernelGGL(k_fft_y, grid, dim3(kBlock), lds, s, S, g, p, tw, TX, inverse, st,
-                     need_mode);
+template <int EMAX, bool INV>
+__global__ __launch_bounds__(kBlock) void k_fft_y(float2* __restrict__ S, Geom g, FFTPlan p,
+                                                  const float2* __restrict__ tw, int lgTX,
+                                                  const State* st, int need_mode) {
+  if (!gate(st, need_mode)) return;
+  extern __shared__ float2 sm[];
+  const int N = g.ny, hx = g.hx, hs = g.hs, ls = N + 1;
+  const int TX = 1 << lgTX;
+  const int kx0 = blockIdx.x * TX;
+  float2* base = S + (long long)blockIdx.z * g.nspec + (long long)blockIdx.y * g.ny * hs;
+  tile_load<EMAX, INV>(sm, base, lgTX, N, ls, hx, kx0, hs);
+  lds_fft<EMAX>(sm, ls, TX, p, tw);
+  tile_store<INV>(sm, base, lgTX, N, ls, hx, kx0, hs);
 }
 
-// ----------------------------------------------------------- z pass + K ----
+void launch_fft_y(float2* S, const Geom& g, const FFTPlan& p, const float2* tw, int inverse,
+                  const State* st, int need_mode, hipStream_t s) {
+  int emax;
+  const int TX = tile_cols(g.ny, &emax);
+  dim3 grid((g.hx + TX - 1) / TX, g.nz, 3);
+  const size_t lds = (size_t)TX * (g.ny + 1) * sizeof(float2);
+#define LAUNCH_Y(E, I)                                                                          \
+  hipLaunchKernelGGL((k_fft_y<E, I>), grid, dim3(kBlock), lds, s, S, g, p, tw, ilog2(TX), st, \
+                     need_mode)
+  if (emax == 8) {
+    if (inverse) LAUNCH_Y(8, true); else LAUNCH_Y(8, false);
+  } else if (emax == 16) {
+    if (inverse) LAUNCH_Y(16, true); else LAUNCH_Y(16, false);
+  } else {
+    if (inverse) LAUNCH_Y(32, true); else LAUNCH_Y(32, false);
+  }
+#undef LAUNCH_Y
+}
 
+template <int EMAX>
 __global__ __launch_bounds__(kBlock) void k_fft_z_K(float2* __restrict__ S, Geom g, FFTPlan p,
-                                                    const float2* __restrict__ tw, int TX,
+                                                    const float2* __restrict__ tw, int lgTX,
                                                     const double* __restrict__ lamx,
                                                     const double* __restrict__ lamy,
                                                     const double* __restrict__ lamz, double alpha,
                                                     double gamma, const State* st, int need_mode) {
   if (!gate(st, need_mode)) return;
   extern __shared__ float2 sm[];
-  const int N = g.nz, hx = g.hx;
+  const int N = g.nz, hx = g.hx, ls = N + 1;
+  const int TX = 1 << lgTX;
   const int kx0 = blockIdx.x * TX;
   const int ky = blockIdx.y;
-  const long long zs = (long long)g.ny * hx;
-  float2* base = S + (long long)blockIdx.z * g.nspec + (long long)ky * hx;
-  for (int e = threadIdx.x; e < TX * N; e += kBlock) {
-    const int c = e % TX, z = e / TX;
-    float2 v = make_float2(0.f, 0.f);
-    if (kx0 + c < hx) v = base[(long long)z * zs + kx0 + c];
-    sm[c * N + z] = v;
-  }
-  __syncthreads();
-  lds_fft(sm, TX, p, tw);
+  const int zs = g.ny * g.hs;
+  float2* base = S + (long long)blockIdx.z * g.nspec + (long long)ky * g.hs;
+  tile_load<EMAX, false>(sm, base, lgTX, N, ls, hx, kx0, zs);
+  lds_fft<EMAX>(sm, ls, TX, p, tw);
   const double inv_n = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
+  const double lyy = lamy[ky];
   for (int e = threadIdx.x; e < TX * N; e += kBlock) {
-    const int c = e / N, kz = e - c * N;
+    const int c = (int)fdiv((uint32_t)e, g.fz), kz = e - c * N;
     const int kx = kx0 + c < hx ? kx0 + c : 0;
-    const double lam = alpha * (lamx[kx] + lamy[ky] + lamz[kz]) + gamma;
+    const double lam = alpha * (lamx[kx] + lyy + lamz[kz]) + gamma;
     const float kh = (float)(inv_n / (lam * lam));
-    const float2 v = sm[e];
-    sm[e] = make_float2(v.x * kh, -v.y * kh);     // conj(K_hat X / |P|)
+    const float2 v = sm[c * ls + kz];
+    sm[c * ls + kz] = make_float2(v.x * kh, -v.y * kh);     // conj(K_hat X / |P|)
   }
   __syncthreads();
-  lds_fft(sm, TX, p, tw);
-  for (int e = threadIdx.x; e < TX * N; e += kBlock) {
-    const int c = e % TX, z = e / TX;
-    if (kx0 + c < hx) base[(long long)z * zs + kx0 + c] = cconj(sm[c * N + z]);
-  }
+  lds_fft<EMAX>(sm, ls, TX, p, tw);
+  tile_store<true>(sm, base, lgTX, N, ls, hx, kx0, zs);
 }
 
 void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
                     const double* lamx, const double* lamy, const double* lamz, double alpha,
                     double gamma, const State* st, int need_mode, hipStream_t s) {
-  const int TX = tile_cols(g.nz);
+  int emax;
+  const int TX = tile_cols(g.nz, &emax);
   dim3 grid((g.hx + TX - 1) / TX, g.ny, 3);
-  const size_t lds = (size_t)TX * g.nz * sizeof(float2);
-  hipLaunchKernelGGL(k_fft_z_K, grid, dim3(kBlock), lds, s, S, g, p, tw, TX, lamx, lamy, lamz,
-                     alpha, gamma, st, need_mode);
+  const size_t lds = (size_t)TX * (g.nz + 1) * sizeof(float2);
+#define LAUNCH_Z(E)                                                                             \
+  hipLaunchKernelGGL(k_fft_z_K<E>, grid, dim3(kBlock), lds, s, S, g, p, tw, ilog2(TX), lamx,  \
+                     lamy, lamz, alpha, gamma, st, need_mode)
+  if (emax == 8)
+    LAUNCH_Z(8);
+  else if (emax == 16)
+    LAUNCH_Z(16);
+  else
+    LAUNCH_Z(32);
+#undef LAUNCH_Z
 }
 
 // ----------------------------------------------------- x inverse + update ----
@@ -384,54 +575,70 @@ void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw
 // (Z'[k] = A[k] + i B[k] for k < hx, conj A[N-k] + i conj B[N-k] above),
 // invert, and split real / imaginary parts back into the two real lines.
 
+template <int EMAX>
 __global__ __launch_bounds__(kBlock) void k_fft_x_inv(const float2* __restrict__ S, Geom g,
                                                       FFTPlan p, const float2* __restrict__ tw,
                                                       int ppb, UpdArgs u) {
   const State* st = u.st;
   if (!gate(st, u.need_mode)) return;
   extern __shared__ float2 sm[];
-  const int N = g.nx, hx = g.hx;
+  const int N = g.nx, hx = g.hx, hs = g.hs;
   const long long n = g.n;
   const int nrows = g.ny * g.nz;
   const int pair0 = blockIdx.x * ppb;
   const int nl = 3 * ppb;
-  for (int e = threadIdx.x; e < nl * N; e += kBlock) {
-    const int l = e / N, k = e - l * N;
-    const int pp = l / 3, which = l - 3 * pp;
-    const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
-    const bool lo = k < hx;
-    const int kk = lo ? k : N - k;
+  const int tot = nl * N;
+  float2 tA[EMAX], tB[EMAX];
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const int e = threadIdx.x + r * kBlock;
     float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-    if (which == 0) {
-      if (r0 < nrows) {
-        A = S[(long long)r0 * hx + kk];
-        B = S[g.nspec + (long long)r0 * hx + kk];
+    if (e < tot) {
+      const int l = (int)fdiv((uint32_t)e, g.fx), k = e - l * N;
+      const int pp = l / 3, which = l - 3 * pp;
+      const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
+      const int kk = k < hx ? k : N - k;
+      if (which == 0) {
+        if (r0 < nrows) {
+          A = S[(long long)r0 * hs + kk];
+          B = S[g.nspec + (long long)r0 * hs + kk];
+        }
+      } else if (which == 1) {
+        if (r1 < nrows) {
+          A = S[(long long)r1 * hs + kk];
+          B = S[g.nspec + (long long)r1 * hs + kk];
+        }
+      } else {
+        if (r0 < nrows) A = S[2 * g.nspec + (long long)r0 * hs + kk];
+        if (r1 < nrows) B = S[2 * g.nspec + (long long)r1 * hs + kk];
       }
-    } else if (which == 1) {
-      if (r1 < nrows) {
-        A = S[(long long)r1 * hx + kk];
-        B = S[g.nspec + (long long)r1 * hx + kk];
+    }
+    tA[r] = A;
+    tB[r] = B;
+  }
+#pragma unroll
+  for (int r = 0; r < EMAX; ++r) {
+    const int e = threadIdx.x + r * kBlock;
+    if (e < tot) {
+      const int k = e - (int)fdiv((uint32_t)e, g.fx) * N;
+      float2 A = tA[r], B = tB[r];
+      if (k >= hx) {
+        A = cconj(A);
+        B = cconj(B);
       }
-    } else {
-      if (r0 < nrows) A = S[2 * g.nspec + (long long)r0 * hx + kk];
-      if (r1 < nrows) B = S[2 * g.nspec + (long long)r1 * hx + kk];
+      // Z = A + i B ; store conj(Z) for the forward transform of the inverse
+      sm[e] = make_float2(A.x - B.y, -(A.y + B.x));
     }
-    if (!lo) {
-      A = cconj(A);
-      B = cconj(B);
-    }
-    // Z = A + i B ; store conj(Z) for the forward transform of the inverse
-    sm[e] = make_float2(A.x - B.y, -(A.y + B.x));
   }
   __syncthreads();
-  lds_fft(sm, nl, p, tw);
+  lds_fft<EMAX>(sm, N, nl, p, tw);
   // result z = conj(DFT(conj Z)): real line a = Re z = Re y, b = Im z = -Im y
   float* vA = u.vA;
   float* vB = u.vB;
   const int base = st->base;
   const float eps = (float)st->eps;
   for (int e = threadIdx.x; e < 2 * ppb * N; e += kBlock) {
-    const int q = e / N, x = e - q * N;
+    const int q = (int)fdiv((uint32_t)e, g.fx), x = e - q * N;
     const int pp = q >> 1, half = q & 1;
     const int row = 2 * (pair0 + pp) + half;
     if (row >= nrows) continue;
@@ -462,11 +669,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(const float2* __restrict__
 
 void launch_fft_x_inv(const float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
                       const UpdArgs& u, hipStream_t s) {
-  const int ppb = pairs_per_block(g.nx);
+  int emax;
+  const int ppb = pairs_per_block(g.nx, &emax);
   const int npairs = (g.ny * g.nz + 1) / 2;
   const int grid = (npairs + ppb - 1) / ppb;
   const size_t lds = (size_t)3 * ppb * g.nx * sizeof(float2);
-  hipLaunchKernelGGL(k_fft_x_inv, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
+  if (emax == 8)
+    hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
+  else if (emax == 16)
+    hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
+  else
+    hipLaunchKernelGGL(k_fft_x_inv<32>, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
 }
 
 }  // namespace lddmm

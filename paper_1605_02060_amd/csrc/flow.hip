@@ -12,9 +12,19 @@
 
 namespace lddmm {
 
+// Blocks of a sweep kernel: a multiple of the 8 XCDs, at most g_sweep_blocks.
+static int g_sweep_blocks = 2048;
+
+void set_sweep_blocks(int b) {
+  b = (b + kXCD - 1) / kXCD * kXCD;
+  g_sweep_blocks = b < kXCD ? kXCD : (b > kPartMax ? kPartMax : b);
+}
+
 int reduce_grid(long long n) {
   long long b = (n + kBlock - 1) / kBlock;
-  return (int)(b < kPartMax ? (b < 1 ? 1 : b) : kPartMax);
+  b = (b + kXCD - 1) / kXCD * kXCD;
+  if (b > g_sweep_blocks) b = g_sweep_blocks;
+  return (int)(b < kXCD ? kXCD : b);
 }
 
 static inline unsigned grid1d(long long n) {
@@ -29,10 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_pad(const float* __restrict__ src, i
                                                 int Nz, float* __restrict__ dst, Geom g) {
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < g.n;
        i += (long long)gridDim.x * kBlock) {
-    const int x = (int)(i % g.nx);
-    const long long t = i / g.nx;
-    const int y = (int)(t % g.ny);
-    const int z = (int)(t / g.ny);
+    int x, y, z;
+    vcoord(g, (uint32_t)i, x, y, z);
     float v = 0.f;
     if (x < Nx && y < Ny && z < Nz) v = src[((long long)z * Ny + y) * Nx + x];
     dst[i] = v;
@@ -57,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_down2(const float* __restrict__ src,
     const int y = (int)(t % c.ny);
     const int z = (int)(t / c.ny);
     const float* p = src + fld * f.n + vidx(f, 2 * x, 2 * y, 2 * z);
-    const long long sy = f.nx, sz = (long long)f.nx * f.ny;
+    const int sy = f.nx, sz = f.nx * f.ny;
     const float s = ((p[0] + p[1]) + (p[sy] + p[sy + 1])) + ((p[sz] + p[sz + 1]) + (p[sz + sy] + p[sz + sy + 1]));
     dst[i] = 0.125f * s;
   }
@@ -104,69 +112,69 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
   const State* st = a.st;
   if (st->mode == MODE_STOPPED) return;
   const Geom g = a.g;
-  const long long n = g.n;
-  const float* __restrict__ v = (st->eval ? a.vB : a.vA) + (long long)a.j * 3 * n;
+  const long long N = g.n;
+  const uint32_t n = (uint32_t)N;
+  const float* vb = (st->eval ? a.vB : a.vA) + (long long)a.j * 3 * N;
+  const rsrc_t V0 = rsrc(vb, n), V1 = rsrc(vb + N, n), V2 = rsrc(vb + 2 * N, n);
+  const rsrc_t U0 = rsrc(a.u_cur, n), U1 = rsrc(a.u_cur + N, n), U2 = rsrc(a.u_cur + 2 * N, n);
+  const rsrc_t W0 = rsrc(a.u_next, n), W1 = rsrc(a.u_next + N, n), W2 = rsrc(a.u_next + 2 * N, n);
+  rsrc_t T0[NC], OUT[NC], T1[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    T0[c] = rsrc(a.J0 + (long long)a.ch[c] * N, n);
+    T1[c] = rsrc(a.J1 + (long long)a.ch[c] * N, n);
+    OUT[c] = rsrc((LAST ? a.r : a.J0t_next) + (long long)c * N, n);
+  }
+  const int ic = a.img_ch >= 0 ? a.img_ch : 0;
+  const rsrc_t IM0 = rsrc(a.J0 + (long long)ic * N, n), IM1 = rsrc(a.J1 + (long long)ic * N, n);
+  const bool mon = LAST && a.img_ch >= 0 && !a.img_weighted;
   const float dt = a.dt, ih = g.inv_h;
-  const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+  const float c2 = a.alpha * ih * ih;
   double accR = 0.0, accD = 0.0, accI = 0.0;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock) {
-    const int x = (int)(i % g.nx);
-    const long long t = i / g.nx;
-    const int y = (int)(t % g.ny);
-    const int z = (int)(t / g.ny);
-    const float vx = v[i], vy = v[i + n], vz = v[i + 2 * n];
+  const XcdRange rg = xcd_range(n);
+  for (uint32_t i = rg.first; i < rg.end; i += rg.stride) {
+    int x, y, z;
+    vcoord(g, i, x, y, z);
+    const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
     float ux = -dt * vx, uy = -dt * vy, uz = -dt * vz;
     if (!FIRST) {
-      int cx, cy, cz;
-      float fx, fy, fz;
-      cell_clamp(x, -dt * vx * ih, g.nx, cx, fx);
-      cell_clamp(y, -dt * vy * ih, g.ny, cy, fy);
-      cell_clamp(z, -dt * vz * ih, g.nz, cz, fz);
-      const float* __restrict__ u = a.u_cur;
-      ux += tri_clamped(u, g, cx, cy, cz, fx, fy, fz);
-      uy += tri_clamped(u + n, g, cx, cy, cz, fx, fy, fz);
-      uz += tri_clamped(u + 2 * n, g, cx, cy, cz, fx, fy, fz);
+      const Cell cl = make_cell_clamp(g, x, y, z, -dt * vx * ih, -dt * vy * ih, -dt * vz * ih);
+      ux += sample(U0, cl);
+      uy += sample(U1, cl);
+      uz += sample(U2, cl);
     }
-    a.u_next[i] = ux;
-    a.u_next[i + n] = uy;
-    a.u_next[i + 2 * n] = uz;
+    bst(W0, i, ux);
+    bst(W1, i, uy);
+    bst(W2, i, uz);
     // deformed templates at t_{j+1}
     {
-      int cx, cy, cz;
-      float fx, fy, fz;
-      cell_free(x, ux * ih, g.nx, cx, fx);
-      cell_free(y, uy * ih, g.ny, cy, fy);
-      cell_free(z, uz * ih, g.nz, cz, fz);
+      const Cell cz = make_cell_zero(g, x, y, z, ux * ih, uy * ih, uz * ih);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const float val = tri_zero(a.J0 + (long long)a.ch[c] * n, g, cx, cy, cz, fx, fy, fz);
+        const float val = sample(T0[c], cz);
         if (!LAST) {
-          a.J0t_next[(long long)c * n + i] = val;
+          bst(OUT[c], i, val);
         } else {
-          const float r = val - a.J1[(long long)a.ch[c] * n + i];
-          a.r[(long long)c * n + i] = r;
+          const float r = val - bld(T1[c], i);
+          bst(OUT[c], i, r);
           accD += (double)a.w[c] * (double)r * (double)r;
           if (a.img_weighted && c == a.img_slot) accI += (double)r * (double)r;
         }
       }
-      if (LAST && a.img_ch >= 0 && !a.img_weighted) {
-        const float val = tri_zero(a.J0 + (long long)a.img_ch * n, g, cx, cy, cz, fx, fy, fz);
-        const float d = val - a.J1[(long long)a.img_ch * n + i];
+      if (mon) {
+        const float d = sample(IM0, cz) - bld(IM1, i);
         accI += (double)d * (double)d;
       }
     }
     // |L v_j|^2 with L = gamma - alpha Lap (periodic 7-point)
     {
-      const float c2 = a.alpha * ih * ih;
-      const float lx = a.gamma * vx - c2 * lap7(v, g, i, x, y, z);
-      const float ly = a.gamma * vy - c2 * lap7(v + n, g, i, x, y, z);
-      const float lz = a.gamma * vz - c2 * lap7(v + 2 * n, g, i, x, y, z);
+      const Nbr nb = periodic_nbr(g, i, x, y, z);
+      const float lx = a.gamma * vx - c2 * lap7_b(V0, nb, vx);
+      const float ly = a.gamma * vy - c2 * lap7_b(V1, nb, vy);
+      const float lz = a.gamma * vz - c2 * lap7_b(V2, nb, vz);
       accR += (double)lx * lx + (double)ly * ly + (double)lz * lz;
     }
   }
-  (void)sy;
-  (void)sz;
   const double sR = block_sum(accR);
   if (threadIdx.x == 0) a.partR[blockIdx.x] = sR;
   if (LAST) {
@@ -207,46 +215,51 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
   const State* st = a.st;
   if (a.need_mode >= 0 && st->mode != a.need_mode) return;
   const Geom g = a.g;
-  const long long n = g.n;
+  const long long N = g.n;
+  const uint32_t n = (uint32_t)N;
   const float dt = a.dt, ih = g.inv_h;
-  const long long sy = g.nx, sz = (long long)g.nx * g.ny;
-  const float* __restrict__ vb = a.vfix ? a.vfix : (st->base ? a.vB : a.vA);
+  const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)(g.nx * g.ny);
+  const float* vb = (a.vfix ? a.vfix : (st->base ? a.vB : a.vA)) +
+                    (long long)(a.j >= 0 ? a.j : 0) * 3 * N;
+  const rsrc_t V0 = rsrc(vb, n), V1 = rsrc(vb + N, n), V2 = rsrc(vb + 2 * N, n);
+  const float* un = a.u_next ? a.u_next : a.u_cur;   // unused when UZERO and !HAS_B
+  const rsrc_t N0 = rsrc(un, n), N1 = rsrc(un + N, n), N2 = rsrc(un + 2 * N, n);
+  float* uc = a.u_cur ? a.u_cur : a.b;               // unused when !HAS_U
+  const rsrc_t C0 = rsrc(uc, n), C1 = rsrc(uc + N, n), C2 = rsrc(uc + 2 * N, n);
+  const rsrc_t B0 = rsrc(a.b, n), B1 = rsrc(a.b + N, n), B2 = rsrc(a.b + 2 * N, n);
+  rsrc_t RR[NC], JJ[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    RR[c] = rsrc(a.r + (long long)c * N, n);
+    JJ[c] = rsrc(a.J0t + (long long)c * a.cstride, n);
+  }
   double mind = 1e300;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock) {
-    const int x = (int)(i % g.nx);
-    const long long t = i / g.nx;
-    const int y = (int)(t % g.ny);
-    const int z = (int)(t / g.ny);
+  const XcdRange rg = xcd_range(n);
+  for (uint32_t i = rg.first; i < rg.end; i += rg.stride) {
+    int x, y, z;
+    vcoord(g, i, x, y, z);
     if (HAS_U) {
-      const float* __restrict__ v = vb + (long long)a.j * 3 * n;
-      const float vx = v[i], vy = v[i + n], vz = v[i + 2 * n];
+      const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
       float ux = dt * vx, uy = dt * vy, uz = dt * vz;
       if (!UZERO) {
-        int cx, cy, cz;
-        float fx, fy, fz;
-        cell_clamp(x, dt * vx * ih, g.nx, cx, fx);
-        cell_clamp(y, dt * vy * ih, g.ny, cy, fy);
-        cell_clamp(z, dt * vz * ih, g.nz, cz, fz);
-        const float* __restrict__ u = a.u_next;
-        ux += tri_clamped(u, g, cx, cy, cz, fx, fy, fz);
-        uy += tri_clamped(u + n, g, cx, cy, cz, fx, fy, fz);
-        uz += tri_clamped(u + 2 * n, g, cx, cy, cz, fx, fy, fz);
+        const Cell cl = make_cell_clamp(g, x, y, z, dt * vx * ih, dt * vy * ih, dt * vz * ih);
+        ux += sample(N0, cl);
+        uy += sample(N1, cl);
+        uz += sample(N2, cl);
       }
-      a.u_cur[i] = ux;
-      a.u_cur[i + n] = uy;
-      a.u_cur[i + 2 * n] = uz;
+      bst(C0, i, ux);
+      bst(C1, i, uy);
+      bst(C2, i, uz);
     }
     if (HAS_B) {
-      const float* __restrict__ u = a.u_next;   // u1 at time jb
-      // Jacobian matrix I + D u (rows: component, columns: direction)
+      // Jacobian matrix I + D u of u1 at time jb (rows: component, columns: direction)
       float J[3][3];
+      const rsrc_t nr[3] = {N0, N1, N2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float* uc = u + c * n;
-        J[c][0] = dstencil(uc, i, x, g.nx, 1, ih);
-        J[c][1] = dstencil(uc, i, y, g.ny, sy, ih);
-        J[c][2] = dstencil(uc, i, z, g.nz, sz, ih);
+        J[c][0] = dstencil_b(nr[c], i, x, g.nx, 1u, ih);
+        J[c][1] = dstencil_b(nr[c], i, y, g.ny, sy, ih);
+        J[c][2] = dstencil_b(nr[c], i, z, g.nz, sz, ih);
       }
       J[0][0] += 1.f;
       J[1][1] += 1.f;
@@ -255,24 +268,20 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
       mind = fmin(mind, (double)det);
-      int cx, cy, cz;
-      float fx, fy, fz;
-      cell_free(x, u[i] * ih, g.nx, cx, fx);
-      cell_free(y, u[i + n] * ih, g.ny, cy, fy);
-      cell_free(z, u[i + 2 * n] * ih, g.nz, cz, fz);
+      const Cell cz = make_cell_zero(g, x, y, z, bld(N0, i) * ih, bld(N1, i) * ih,
+                                     bld(N2, i) * ih);
       float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const float rw = a.w[c] * tri_zero(a.r + (long long)c * n, g, cx, cy, cz, fx, fy, fz);
-        const float* Jc = a.J0t + (long long)c * a.cstride;
-        bx += rw * dstencil(Jc, i, x, g.nx, 1, ih);
-        by += rw * dstencil(Jc, i, y, g.ny, sy, ih);
-        bz += rw * dstencil(Jc, i, z, g.nz, sz, ih);
+        const float rw = a.w[c] * sample(RR[c], cz);
+        bx += rw * dstencil_b(JJ[c], i, x, g.nx, 1u, ih);
+        by += rw * dstencil_b(JJ[c], i, y, g.ny, sy, ih);
+        bz += rw * dstencil_b(JJ[c], i, z, g.nz, sz, ih);
       }
       const float s = a.coef * det;
-      a.b[i] = s * bx;
-      a.b[i + n] = s * by;
-      a.b[i + 2 * n] = s * bz;
+      bst(B0, i, s * bx);
+      bst(B1, i, s * by);
+      bst(B2, i, s * bz);
     }
   }
   if (HAS_B) {

@@ -10,24 +10,48 @@
 namespace lddmm {
 
 constexpr int kBlock = 256;        // threads per block for every kernel
-constexpr int kPartMax = 1024;     // max blocks of a reducing kernel (partials per launch)
+constexpr int kPartMax = 4096;     // max blocks of a reducing kernel (partials per launch)
 constexpr int kMaxStages = 12;     // radix stages of one 1D transform
-constexpr int kFFTElems = 4096;    // complex values held in LDS by one FFT block (32 KB)
-constexpr int kEMax = 16;          // complex values one thread holds across an LDS stage
+constexpr int kFFTElems = 2048;    // complex values held in LDS by one FFT block (16 KB)
+constexpr int kEMax = 8;           // complex values one thread holds across an LDS stage
+constexpr int kXCD = 8;            // accelerator complex dies of an MI355X
+
+// Unsigned division by a runtime constant d via a precomputed multiplier:
+// q = (umulhi(n, m) + n) >> s, exact for every n < 2^31 (all indices here are
+// below 2^31 because each axis is at most LDDMM_MAX_DIM = 1024).
+struct FastDiv {
+  uint32_t d, m;
+  int s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  int s = 0;
+  while ((1ull << s) < d) ++s;
+  const unsigned long long m = ((1ull << 32) * ((1ull << s) - d)) / d + 1;
+  return FastDiv{d, (uint32_t)m, s};
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (__umulhi(n, f.m) + n) >> f.s;
+}
 
 // Computational grid of one pyramid level.
 struct Geom {
   int nx, ny, nz;   // P (each axis 7-smooth)
   int hx;           // nx/2 + 1: length of the half spectrum along x
-  long long n;      // nx*ny*nz
-  long long nspec;  // hx*ny*nz
+  int hs;           // row stride of the half spectrum: hx rounded up to 16
+  long long n;      // nx*ny*nz (< 2^30)
+  long long nspec;  // hs*ny*nz
   float h, inv_h;   // spacing and its inverse
+  FastDiv fx, fy, fz, fhx;   // division by nx, ny, nz, hx
 };
 
 // Mixed-radix factorisation of one transform length (radices 2,3,4,5,7,8).
 struct FFTPlan {
   int n, nst;
   int radix[kMaxStages];
+  FastDiv fnb[kMaxStages];   // division by n / radix[s]
+  FastDiv fns[kMaxStages];   // division by the product of the previous radices
 };
 
 // Device-side control state of the descent (one per problem).
@@ -119,6 +143,7 @@ void launch_down2(const float* src, const Geom& fine, float* dst, const Geom& co
 void launch_up2(const float* src, const Geom& coarse, float* dst, const Geom& fine, int nfields,
                 hipStream_t s);
 int reduce_grid(long long n);
+void set_sweep_blocks(int blocks);
 void launch_forward(const FwdArgs& a, hipStream_t s);
 void launch_backward(const BwdArgs& a, hipStream_t s);
 void launch_crop3(const float* u, const Geom& g, int Nx, int Ny, int Nz, float* out,

@@ -3,11 +3,54 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "internal.h"
 #include "lddmm.h"
 
 namespace lddmm {
+
+// ------------------------------------------------------------ profiling ----
+// Events bracket each launch of an enabled class on its own stream.
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  long long vox;
+};
+static unsigned g_prof_mask = 0;
+static long long g_prof_min_vox = 0;
+static std::vector<ProfRec> g_prof_rec;
+static std::vector<hipEvent_t> g_prof_pool;
+static size_t g_prof_used = 0;
+
+static hipEvent_t prof_event() {
+  if (g_prof_used == g_prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof_pool.push_back(e);
+  }
+  return g_prof_pool[g_prof_used++];
+}
+
+struct ProfScope {
+  int cls;
+  long long vox;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(int c, long long n, hipStream_t st) : cls(c), vox(n), s(st) {
+    if ((g_prof_mask & (1u << cls)) && vox >= g_prof_min_vox) {
+      a = prof_event();
+      if (a) hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event();
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_prof_rec.push_back({cls, a, b, vox});
+  }
+};
 
 static bool is_7smooth(int n) {
   for (int p : {2, 3, 5, 7})
@@ -33,10 +76,15 @@ static Geom make_geom(int nx, int ny, int nz, double h) {
   g.ny = ny;
   g.nz = nz;
   g.hx = nx / 2 + 1;
+  g.hs = (g.hx + 15) / 16 * 16;
   g.n = (long long)nx * ny * nz;
-  g.nspec = (long long)g.hx * ny * nz;
+  g.nspec = (long long)g.hs * ny * nz;
   g.h = (float)h;
   g.inv_h = (float)(1.0 / h);
+  g.fx = make_fastdiv((uint32_t)nx);
+  g.fy = make_fastdiv((uint32_t)ny);
+  g.fz = make_fastdiv((uint32_t)nz);
+  g.fhx = make_fastdiv((uint32_t)g.hx);
   return g;
 }
 
@@ -93,6 +141,7 @@ static int check_params(const lddmm_grid* grid, const lddmm_params* p, int multi
   if (grid->nx > LDDMM_MAX_DIM || grid->ny > LDDMM_MAX_DIM || grid->nz > LDDMM_MAX_DIM)
     return LDDMM_EINVAL;
   if (!(grid->spacing > 0.0) || !std::isfinite(grid->spacing)) return LDDMM_EINVAL;
+  if ((long long)grid->nx * grid->ny * grid->nz >= (1LL << 29)) return LDDMM_EINVAL;
   if (!(p->alpha >= 0.0) || !(p->gamma > 0.0) || !(p->sigma > 0.0)) return LDDMM_EINVAL;
   if (!std::isfinite(p->alpha) || !std::isfinite(p->gamma) || !std::isfinite(p->sigma))
     return LDDMM_EINVAL;
@@ -262,6 +311,7 @@ static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool
     a.partD = c.partD;
     a.partI = c.partI;
     a.st = c.st;
+    ProfScope ps(LDDMM_PROF_FORWARD, n, s);
     launch_forward(a, s);
   }
 }
@@ -275,12 +325,28 @@ static float* u0_final(Ctx& c, int li, bool keep_all) {
 // K smoothing of c.b followed by the x-inverse epilogue.
 static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, hipStream_t s) {
   const Level& L = c.cfg.lv[li];
-  launch_fft_x_fwd(c.b, c.S, L.g, L.px, c.tw[0], c.st, need_mode, s);
-  launch_fft_y(c.S, L.g, L.py, c.tw[1], 0, c.st, need_mode, s);
-  launch_fft_z_K(c.S, L.g, L.pz, c.tw[2], c.lam[0], c.lam[1], c.lam[2], c.alpha, c.gamma, c.st,
-                 need_mode, s);
-  launch_fft_y(c.S, L.g, L.py, c.tw[1], 1, c.st, need_mode, s);
-  launch_fft_x_inv(c.S, L.g, L.px, c.tw[0], u, s);
+  const long long n = L.g.n;
+  {
+    ProfScope ps(LDDMM_PROF_FFT_X, n, s);
+    launch_fft_x_fwd(c.b, c.S, L.g, L.px, c.tw[0], c.st, need_mode, s);
+  }
+  {
+    ProfScope ps(LDDMM_PROF_FFT_Y, n, s);
+    launch_fft_y(c.S, L.g, L.py, c.tw[1], 0, c.st, need_mode, s);
+  }
+  {
+    ProfScope ps(LDDMM_PROF_FFT_ZK, n, s);
+    launch_fft_z_K(c.S, L.g, L.pz, c.tw[2], c.lam[0], c.lam[1], c.lam[2], c.alpha, c.gamma,
+                   c.st, need_mode, s);
+  }
+  {
+    ProfScope ps(LDDMM_PROF_FFT_YINV, n, s);
+    launch_fft_y(c.S, L.g, L.py, c.tw[1], 1, c.st, need_mode, s);
+  }
+  {
+    ProfScope ps(LDDMM_PROF_FFT_XINV, n, s);
+    launch_fft_x_inv(c.S, L.g, L.px, c.tw[0], u, s);
+  }
 }
 
 // Backward sweep: maps u1_j, body forces b_j, K b_j and the epilogue per j.
@@ -320,7 +386,10 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
     a.st = c.st;
     a.need_mode = need_mode;
     if (a.j < 0 && a.jb < 0) continue;
-    launch_backward(a, s);
+    {
+      ProfScope ps(LDDMM_PROF_BACKWARD, n, s);
+      launch_backward(a, s);
+    }
     if (a.jb >= 0) {
       UpdArgs u{};
       u.kind = upd_kind;
@@ -340,6 +409,7 @@ static void decide(Ctx& c, int li, int init, double* trace, hipStream_t s) {
   const Level& L = c.cfg.lv[li];
   const int nb = reduce_grid(L.g.n);
   const double h = (double)L.g.h;
+  ProfScope ps(LDDMM_PROF_OTHER, 0, s);
   launch_decide(c.st, c.partR, c.cfg.T, c.partD, c.partI, c.partDet, nb, nb, c.cfg.C > 1,
                 1.0 / c.cfg.T, h * h * h, 1.0 / (c.sigma * c.sigma), c.guard, trace, init, s);
 }
@@ -490,7 +560,10 @@ int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm
     decide(c, li, 1, trace, s);
     for (int it = 0; it < prm->iters[li]; ++it) {
       backward_sweep(c, li, c.v[0], c.v[1], nullptr, true, UPD_STEP, nullptr, MODE_GRAD, s);
-      launch_retry(c.v[0], c.v[1], 3 * L.g.n * k.T, c.st, s);
+      {
+        ProfScope ps(LDDMM_PROF_OTHER, 0, s);
+        launch_retry(c.v[0], c.v[1], 3 * L.g.n * k.T, c.st, s);
+      }
       forward_sweep(c, li, c.v[0], c.v[1], false, s);
       decide(c, li, 0, trace, s);
     }
@@ -579,7 +652,7 @@ size_t lddmm_smooth_workspace_size(const int32_t P[3]) {
   if (!P) return 0;
   for (int d = 0; d < 3; ++d)
     if (P[d] < 2 || P[d] > LDDMM_MAX_DIM || !is_7smooth(P[d])) return 0;
-  const size_t nspec = (size_t)(P[0] / 2 + 1) * P[1] * P[2];
+  const size_t nspec = (size_t)((P[0] / 2 + 1 + 15) / 16 * 16) * P[1] * P[2];
   size_t off = align_up(sizeof(State));
   for (int d = 0; d < 3; ++d) off = align_up(off + sizeof(float2) * P[d]);
   for (int d = 0; d < 3; ++d) off = align_up(off + sizeof(double) * P[d]);
@@ -639,6 +712,48 @@ int lddmm_make_mask(const lddmm_grid* grid, const float* image, float tau, float
   launch_make_mask(image, (long long)grid->nx * grid->ny * grid->nz, tau, mask, masked_image,
                    (hipStream_t)stream);
   return hip_status();
+}
+
+int lddmm_set_tunable(int32_t which, int32_t value) {
+  if (which == LDDMM_TUNE_SWEEP_BLOCKS) {
+    if (value < 1) return LDDMM_EINVAL;
+    set_sweep_blocks(value);
+    return LDDMM_OK;
+  }
+  return LDDMM_EINVAL;
+}
+
+int lddmm_profile_begin(uint32_t class_mask, int64_t min_voxels) {
+  g_prof_min_vox = min_voxels;
+  g_prof_rec.clear();
+  g_prof_used = 0;
+  g_prof_mask = class_mask & ((1u << LDDMM_PROF_CLASSES) - 1);
+  return LDDMM_OK;
+}
+
+int lddmm_profile_end(double* ms_total, int64_t* launches, int64_t* voxels) {
+  double ms[LDDMM_PROF_CLASSES] = {0};
+  int64_t cnt[LDDMM_PROF_CLASSES] = {0}, vox[LDDMM_PROF_CLASSES] = {0};
+  int rc = LDDMM_OK;
+  for (const ProfRec& r : g_prof_rec) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      rc = LDDMM_EHIP;
+      continue;
+    }
+    ms[r.cls] += t;
+    cnt[r.cls] += 1;
+    vox[r.cls] += r.vox;
+  }
+  for (int k = 0; k < LDDMM_PROF_CLASSES; ++k) {
+    if (ms_total) ms_total[k] = ms[k];
+    if (launches) launches[k] = cnt[k];
+    if (voxels) voxels[k] = vox[k];
+  }
+  g_prof_mask = 0;
+  g_prof_rec.clear();
+  g_prof_used = 0;
+  return rc;
 }
 
 const char* lddmm_strerror(int code) {

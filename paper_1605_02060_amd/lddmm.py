@@ -92,6 +92,12 @@ def load():
     lib.lddmm_smooth.restype = ctypes.c_int
     lib.lddmm_make_mask.argtypes = [P(_Grid), vp, ctypes.c_float, vp, vp, vp]
     lib.lddmm_make_mask.restype = ctypes.c_int
+    lib.lddmm_profile_begin.argtypes = [ctypes.c_uint32, ctypes.c_int64]
+    lib.lddmm_profile_begin.restype = ctypes.c_int
+    lib.lddmm_profile_end.argtypes = [vp, vp, vp]
+    lib.lddmm_profile_end.restype = ctypes.c_int
+    lib.lddmm_set_tunable.argtypes = [i32, i32]
+    lib.lddmm_set_tunable.restype = ctypes.c_int
     lib.lddmm_strerror.argtypes = [ctypes.c_int]
     lib.lddmm_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -100,7 +106,13 @@ def load():
 
 EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddmm_register",
             "lddmm_energy", "lddmm_gradient", "lddmm_apply", "lddmm_smooth_workspace_size",
-            "lddmm_smooth", "lddmm_make_mask", "lddmm_strerror"]
+            "lddmm_smooth", "lddmm_make_mask", "lddmm_profile_begin", "lddmm_profile_end",
+            "lddmm_set_tunable", "lddmm_strerror"]
+
+TUNE_SWEEP_BLOCKS = 0
+
+PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
+                "other"]
 
 
 def strerror(code):
@@ -283,3 +295,27 @@ def lddmm_make_mask(image, tau, stream=None):
     _check(load().lddmm_make_mask(ctypes.byref(g), _ptr(image), float(tau), _ptr(m), _ptr(mi),
                                   _stream(stream)), "lddmm_make_mask")
     return m, mi
+
+
+def lddmm_profile_begin(class_mask=0xFF, min_voxels=0):
+    """Record HIP events around every launch of the selected kernel classes
+    whose grid has at least min_voxels voxels."""
+    _check(load().lddmm_profile_begin(int(class_mask), int(min_voxels)), "lddmm_profile_begin")
+
+
+def lddmm_profile_end():
+    """Stop recording; per class: dict(ms=total ms, launches=count, voxels=grid voxels)."""
+    n = len(PROF_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    vox = (ctypes.c_int64 * n)()
+    _check(load().lddmm_profile_end(ctypes.cast(ms, ctypes.c_void_p),
+                                    ctypes.cast(cnt, ctypes.c_void_p),
+                                    ctypes.cast(vox, ctypes.c_void_p)), "lddmm_profile_end")
+    return {name: {"ms": ms[k], "launches": cnt[k], "voxels": vox[k]}
+            for k, name in enumerate(PROF_CLASSES)}
+
+
+def lddmm_set_tunable(which, value):
+    """Set a launch-shape tunable (results do not depend on it, only speed)."""
+    _check(load().lddmm_set_tunable(int(which), int(value)), "lddmm_set_tunable")

@@ -183,8 +183,8 @@ def atlas_pair(shape=(228, 160, 264), seed=1, max_disp=12.0, tau=0.1,
     The target intensity is I1 * S with S ~ Poisson(ln(10/9)) i.i.d., so that
     90% of voxels are zero and the rest are Poisson-count spots (the sparse
     labelling of CLARITY described in the Abstract and Challenges sections).
-    The target mask closes the thresholded sparse image with a ball of radius
-    close_r and then opens it with radius open_r (voxels).
+    The target mask thresholds the sparse image at tau, closes it with a ball
+    of radius close_r and then opens it with radius open_r (voxels).
     """
     rng = np.random.default_rng(seed)
     nz, ny, nx = shape
@@ -206,7 +206,7 @@ def atlas_pair(shape=(228, 160, 264), seed=1, max_disp=12.0, tau=0.1,
     if sparse:
         S = rng.poisson(math.log(10.0 / 9.0), size=shape).astype(np.float64)
         I1s = I1 * S
-        m = I1s > 0
+        m = I1s > tau
         m = _ball_erode(_ball_dilate(m, close_r), close_r)
         m = _ball_dilate(_ball_erode(m, open_r), open_r)
         M1 = m
