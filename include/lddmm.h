@@ -197,7 +197,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * Launch-shape tunables (process-wide; results are identical for every value,
  * only speed changes).  LDDMM_TUNE_SWEEP_BLOCKS: blocks of the forward and
  * backward sweep kernels (rounded to a multiple of 8, clamped to [8, 4096];
- * default 2048).  Returns LDDMM_OK or LDDMM_EINVAL.
+ * default 1024).  Returns LDDMM_OK or LDDMM_EINVAL.
  */
 #define LDDMM_TUNE_SWEEP_BLOCKS 0
 int lddmm_set_tunable(int32_t which, int32_t value);

@@ -199,4 +199,18 @@ void launch_energy_out(const State* st, double* out4, hipStream_t s) {
   hipLaunchKernelGGL(k_energy_out, dim3(1), dim3(64), 0, s, st, out4);
 }
 
+// As k_energy_out, but E is reported as NaN when the splat radius overflowed.
+__global__ void k_energy_out_checked(const State* st, const int* overflow, double* out4) {
+  if (threadIdx.x == 0) {
+    out4[0] = *overflow ? __longlong_as_double(0x7ff8000000000000LL) : st->E;
+    out4[1] = st->R;
+    out4[2] = st->D;
+    out4[3] = st->img;
+  }
+}
+
+void launch_energy_out_checked(const State* st, const int* overflow, double* out4, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_out_checked, dim3(1), dim3(64), 0, s, st, overflow, out4);
+}
+
 }  // namespace lddmm

@@ -51,8 +51,8 @@ __device__ __forceinline__ float lerp_cell(const Cell& c, float v0, float v1, fl
 // XCD-aware work split of a sweep over n voxels.  Blocks are dealt to the 8 XCDs
 // round-robin (block b runs on XCD b mod 8), so the blocks of one XCD take one
 // contiguous eighth of the grid -- a slab of whole z-planes -- and stride through
-// it together: stencil and gather neighbours (rows and planes next to the
-// current window) are then still in that XCD's L2.  gridDim.x is a multiple of 8.
+// it together, keeping stencil and gather neighbours of the current window in
+// that XCD's L2.  gridDim.x is a multiple of 8.
 struct XcdRange {
   uint32_t first, end, stride;
 };

@@ -13,7 +13,7 @@
 namespace lddmm {
 
 // Blocks of a sweep kernel: a multiple of the 8 XCDs, at most g_sweep_blocks.
-static int g_sweep_blocks = 2048;
+static int g_sweep_blocks = 1024;
 
 void set_sweep_blocks(int b) {
   b = (b + kXCD - 1) / kXCD * kXCD;

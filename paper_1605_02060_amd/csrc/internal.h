@@ -169,7 +169,30 @@ void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw
 void launch_fft_x_inv(const float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
                       const UpdArgs& u, hipStream_t s);
 
+// grad.hip
+struct GradArgs {
+  Geom g;
+  int nch;
+  const float* J0;       // template channels [C][n]
+  int ch[2];
+  float wc[2];
+  float coef;            // 2 h^3 / sigma^2
+  const float* r;        // residual [nch][n]
+  const float* u;        // u0 at the step the kernel needs [3][n]
+  const float* v;        // v_j [3][n]
+  const float* ub_in;    // ubar_{j+1} [3][n]
+  float* ub_out;         // ubar_j or ubar_T [3][n]
+  float* w;              // L v_j scratch [3][n]
+  float* grad;           // dE/dv_j [3][n]
+  float dt, alpha, gamma, reg;   // reg = 2 dt h^3
+  const int* radius;     // device: splat radius for this step
+  int* overflow;         // device flag: radius beyond the supported maximum
+};
+void launch_ubar_init(const GradArgs& a, hipStream_t s);
+void launch_grad_step(const GradArgs& a, hipStream_t s);
+
 // control.hip
+void launch_energy_out_checked(const State* st, const int* overflow, double* out4, hipStream_t s);
 void launch_level_begin(State* st, double step, int keep_flags, hipStream_t s);
 void launch_decide(State* st, const double* partR, int T, const double* partD,
                    const double* partI, const double* partDet, int nblk_fwd, int nblk_bwd,

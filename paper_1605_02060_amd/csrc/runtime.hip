@@ -116,7 +116,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t state, partR, partD, partI, partDet, trace, tw[3], lam[3];
-  size_t J0, J1, v0, v1, u0, u1, J0t, r, b, S, ub, total;
+  size_t J0, J1, v0, v1, u0, u1, J0t, r, b, S, ub, misc, total;
   size_t Joff[LDDMM_MAX_LEVELS];   // per-level offsets (floats) inside J0 / J1
   int n_u0;                         // u0 slots
 };
@@ -127,7 +127,37 @@ struct Config {
   int img_ch, img_weighted, img_slot;
   Level lv[LDDMM_MAX_LEVELS];
   int rows;
+  int ck;            // exact gradient: checkpoint spacing (0 = keep every u0_j)
 };
+
+// u0 storage of the exact gradient.  Without recompute slot j holds u0_j.  With
+// checkpoints every ck steps: slots [0, nck) hold u0 at j = 0, ck, 2 ck, ... and
+// T; the next max(2, ck - 1) slots are scratch (ping-pong during the full
+// forward sweep, then the interior steps of the segment being recomputed).
+struct U0Plan {
+  int ck, nck, nslots;
+};
+
+static U0Plan u0_plan(int T, int ck) {
+  U0Plan p{};
+  p.ck = ck;
+  if (ck <= 0 || ck >= T) {
+    p.ck = 0;
+    p.nck = T + 1;
+    p.nslots = T + 1;
+    return p;
+  }
+  p.nck = (T + ck - 1) / ck + 1;
+  p.nslots = p.nck + (ck - 1 > 2 ? ck - 1 : 2);
+  return p;
+}
+
+// Slot of a checkpoint step (j multiple of ck, or T).
+static int ck_slot(const U0Plan& p, int j, int T) {
+  if (p.ck == 0) return j;
+  return j == T ? p.nck - 1 : j / p.ck;
+}
+static bool is_ck(const U0Plan& p, int j, int T) { return p.ck == 0 || j == T || j % p.ck == 0; }
 
 static int trace_rows(const lddmm_params* p) {
   int rows = 0;
@@ -182,6 +212,9 @@ static int make_config(const lddmm_grid* grid, const lddmm_params* p, int has_im
     }
   if (!build_levels(grid, c->L, c->lv)) return LDDMM_EINVAL;
   c->rows = multilevel ? trace_rows(p) : 1;
+  c->ck = (p->flags & LDDMM_FLAG_RECOMPUTE_PHI) ? (p->checkpoint_every > 0 ? p->checkpoint_every
+                                                                            : 1)
+                                                : 0;
   return LDDMM_OK;
 }
 
@@ -214,7 +247,7 @@ static Layout make_layout(const Config& c) {
   o.J1 = take(sizeof(float) * jt);
   o.v0 = take(sizeof(float) * 3 * n * c.T);
   o.v1 = take(sizeof(float) * 3 * n * c.T);
-  o.n_u0 = c.T + 1;
+  o.n_u0 = u0_plan(c.T, c.ck).nslots;
   o.u0 = take(sizeof(float) * 3 * n * o.n_u0);
   o.u1 = take(sizeof(float) * 3 * n * 2);
   o.J0t = take(sizeof(float) * n * c.nch * c.T);
@@ -222,6 +255,7 @@ static Layout make_layout(const Config& c) {
   o.b = take(sizeof(float) * 3 * n);
   o.S = take(sizeof(float2) * 3 * (size_t)gf.nspec);
   o.ub = take(sizeof(float) * 3 * n * 2);
+  o.misc = take(sizeof(int) * 64);
   o.total = align_up(off);
   return o;
 }
@@ -236,6 +270,7 @@ struct Ctx {
   float2* tw[3];
   double* lam[3];
   float *J0, *J1, *v[2], *u0, *u1, *J0t, *r, *b, *ub;
+  int* misc;
   float2* S;
   double alpha, gamma, sigma;
   int guard;
@@ -265,6 +300,7 @@ static void bind(Ctx& c, void* ws) {
   c.b = (float*)(c.ws + o.b);
   c.S = (float2*)(c.ws + o.S);
   c.ub = (float*)(c.ws + o.ub);
+  c.misc = (int*)(c.ws + o.misc);
 }
 
 static void level_tables(Ctx& c, const Level& L, hipStream_t s) {
@@ -275,14 +311,15 @@ static void level_tables(Ctx& c, const Level& L, hipStream_t s) {
   }
 }
 
-// Forward sweep of the velocity selected by st->eval (vA/vB), storing u0 in
-// ping-pong slots (or all T+1 slots when keep_all), deformed templates and r.
-static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool keep_all,
-                          hipStream_t s) {
+// Forward sweep of the velocity selected by st->eval (vA/vB) for steps
+// j in [j_beg, j_end): reads u0_j from slot sl[j], writes u0_{j+1} to slot sl[j+1],
+// plus deformed templates, r and the energy partials.
+static void forward_steps(Ctx& c, int li, const float* vA, const float* vB, const int* sl, int j_beg,
+                          int j_end, hipStream_t s) {
   const Config& k = c.cfg;
   const Level& L = k.lv[li];
   const long long n = L.g.n;
-  for (int j = 0; j < k.T; ++j) {
+  for (int j = j_beg; j < j_end; ++j) {
     FwdArgs a{};
     a.g = L.g;
     a.vA = vA;
@@ -292,9 +329,8 @@ static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool
     a.dt = 1.0f / (float)k.T;
     a.alpha = (float)c.alpha;
     a.gamma = (float)c.gamma;
-    const int sc = keep_all ? j : (j & 1), sn = keep_all ? j + 1 : ((j + 1) & 1);
-    a.u_cur = c.u0 + (long long)sc * 3 * n;
-    a.u_next = c.u0 + (long long)sn * 3 * n;
+    a.u_cur = c.u0 + (long long)sl[j] * 3 * n;
+    a.u_next = c.u0 + (long long)sl[j + 1] * 3 * n;
     a.J0 = c.J0 + c.lay.Joff[li];
     a.J1 = c.J1 + c.lay.Joff[li];
     a.nch = k.nch;
@@ -305,7 +341,7 @@ static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool
     a.img_ch = k.img_ch;
     a.img_weighted = k.img_weighted;
     a.img_slot = k.img_slot;
-    a.J0t_next = c.J0t + (long long)(j + 1) * k.nch * n;
+    a.J0t_next = c.J0t + (long long)(j + 1 < k.T ? j + 1 : 0) * k.nch * n;
     a.r = c.r;
     a.partR = c.partR + (long long)j * kPartMax;
     a.partD = c.partD;
@@ -314,6 +350,13 @@ static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool
     ProfScope ps(LDDMM_PROF_FORWARD, n, s);
     launch_forward(a, s);
   }
+}
+
+static void forward_sweep(Ctx& c, int li, const float* vA, const float* vB, bool keep_all,
+                          hipStream_t s) {
+  int sl[LDDMM_MAX_T + 1];
+  for (int j = 0; j <= c.cfg.T; ++j) sl[j] = keep_all ? j : (j & 1);
+  forward_steps(c, li, vA, vB, sl, 0, c.cfg.T, s);
 }
 
 static float* u0_final(Ctx& c, int li, bool keep_all) {
@@ -402,6 +445,77 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
       u.need_mode = need_mode;
       smooth_and_update(c, li, u, need_mode, s);
     }
+  }
+}
+
+static void decide(Ctx& c, int li, int init, double* trace, hipStream_t s);
+
+// Exact gradient dE/dv (reverse mode) of the single-level energy at v.
+static void exact_gradient(Ctx& c, const float* v, float* grad, hipStream_t s) {
+  const Config& k = c.cfg;
+  const Level& L = k.lv[0];
+  const long long n = L.g.n;
+  const int T = k.T;
+  const U0Plan up = u0_plan(T, k.ck);
+  // full forward sweep, keeping u0 at the checkpoints (every step without recompute)
+  int sl[LDDMM_MAX_T + 1];
+  int scratch = 0;
+  for (int j = 0; j <= T; ++j) {
+    if (is_ck(up, j, T)) {
+      sl[j] = ck_slot(up, j, T);
+    } else {
+      sl[j] = up.nck + (scratch & 1);
+      ++scratch;
+    }
+  }
+  // u0_0 = 0 is implicit in the forward kernels; the reverse step j = 0 reads it
+  launch_fill(c.u0 + (long long)sl[0] * 3 * n, 3 * n, 0.f, s);
+  forward_steps(c, 0, v, v, sl, 0, T, s);
+  decide(c, 0, 1, c.trace, s);
+  GradArgs a{};
+  a.g = L.g;
+  a.nch = k.nch;
+  a.J0 = c.J0;
+  a.ch[0] = k.ch[0];
+  a.ch[1] = k.nch > 1 ? k.ch[1] : k.ch[0];
+  a.wc[0] = k.w[0];
+  a.wc[1] = k.nch > 1 ? k.w[1] : 0.f;
+  const double h = (double)L.g.h;
+  a.coef = (float)(2.0 * h * h * h / (c.sigma * c.sigma));
+  a.r = c.r;
+  a.dt = 1.0f / (float)T;
+  a.alpha = (float)c.alpha;
+  a.gamma = (float)c.gamma;
+  a.reg = (float)(2.0 / T * h * h * h);
+  a.w = c.b;
+  a.radius = c.misc;
+  a.overflow = c.misc + 1;
+  a.u = c.u0 + (long long)sl[T] * 3 * n;
+  a.ub_out = c.ub + (long long)(T & 1) * 3 * n;
+  launch_ubar_init(a, s);
+  int seg_lo = -1;   // first step of the segment whose interior is recomputed
+  for (int j = T - 1; j >= 0; --j) {
+    int uslot;
+    if (is_ck(up, j, T)) {
+      uslot = ck_slot(up, j, T);
+    } else {
+      const int j0 = (j / up.ck) * up.ck;
+      if (seg_lo != j0) {
+        // recompute u0_{j0+1} .. u0_{j} from the checkpoint at j0 into scratch slots
+        int rs[LDDMM_MAX_T + 1];
+        const int j1 = (j0 + up.ck < T ? j0 + up.ck : T);
+        for (int m = j0; m <= j1; ++m) rs[m] = m == j0 ? ck_slot(up, j0, T) : up.nck + (m - j0 - 1);
+        forward_steps(c, 0, v, v, rs, j0, j1 - 1, s);
+        seg_lo = j0;
+      }
+      uslot = up.nck + (j - j0 - 1);
+    }
+    a.u = c.u0 + (long long)uslot * 3 * n;
+    a.v = v + (long long)j * 3 * n;
+    a.ub_in = c.ub + (long long)((j + 1) & 1) * 3 * n;
+    a.ub_out = c.ub + (long long)(j & 1) * 3 * n;
+    a.grad = grad + (long long)j * 3 * n;
+    launch_grad_step(a, s);
   }
 }
 
@@ -618,7 +732,7 @@ int lddmm_energy(const lddmm_problem* p, const lddmm_params* prm, double* out4, 
 int lddmm_gradient(const lddmm_problem* p, const lddmm_params* prm, int32_t kind, float* grad,
                    double* out4, void* stream) {
   if (!grad || !out4) return LDDMM_EINVAL;
-  if (kind != LDDMM_GRAD_V) return LDDMM_EINVAL;
+  if (kind != LDDMM_GRAD_V && kind != LDDMM_GRAD_L2) return LDDMM_EINVAL;
   Ctx c{};
   int rc = prepare(c, p, prm, 0);
   if (rc) return rc;
@@ -626,6 +740,12 @@ int lddmm_gradient(const lddmm_problem* p, const lddmm_params* prm, int32_t kind
   hipGetLastError();
   setup_images(c, p, s);
   launch_level_begin(c.st, 1.0, 0, s);
+  if (kind == LDDMM_GRAD_L2) {
+    launch_fill((float*)c.misc, 2, 0.f, s);   // radius, overflow flag (zero bits)
+    exact_gradient(c, p->v, grad, s);
+    launch_energy_out_checked(c.st, c.misc + 1, out4, s);
+    return hip_status();
+  }
   level_tables(c, c.cfg.lv[0], s);
   forward_sweep(c, 0, p->v, p->v, false, s);
   decide(c, 0, 1, c.trace, s);

@@ -172,6 +172,29 @@ def test_exact_gradient_matches_bruteforce_fd_on_8cubed():
     assert np.abs(g - fd).max() < 2e-6 * scale
 
 
+def test_exact_gradient_matches_bruteforce_fd_on_non_cubic_grid():
+    p = synth.blob_pair((6, 7, 9), 7, max_disp=1.0, sigma=(1.2, 2.0), center_frac=(0.35, 0.65))
+    prob = O.Problem(p.M0 * 0.8 + 0.1 * p.I0, p.M1 * 0.8 + 0.1 * p.I1)
+    T = 2
+    prm = O.Params(T=T, alpha=0.05)
+    J0, J1, P = O._single_level(prob)
+    v = synth.random_velocity(P, T, 8, vmax=0.9, sigma_s=1.5).astype(np.float64)
+    v += 0.05 * np.random.default_rng(9).normal(size=(T, 3) + P)
+    g, _, _ = O.gradient(prob, prm, v, kind="L2")
+    eps = 1e-6
+    fd = np.zeros_like(v)
+    flat = v.reshape(-1)
+    for i in range(flat.size):
+        old = flat[i]
+        flat[i] = old + eps
+        ep = O.energy_terms(v, J0, J1, prm, 1.0)["E"]
+        flat[i] = old - eps
+        em = O.energy_terms(v, J0, J1, prm, 1.0)["E"]
+        flat[i] = old
+        fd.reshape(-1)[i] = (ep - em) / (2 * eps)
+    assert np.abs(g - fd).max() < 2e-6 * np.abs(g).max()
+
+
 def test_exact_gradient_directional_fd_physical_spacing():
     prob = _tiny_problem(11, 10)
     T = 3
