@@ -109,6 +109,98 @@ def cpu_baseline(pair, budget_s=20.0):
                       "single-threaded elementwise and numpy.fft"}
 
 
+def _kernel_rows(db):
+    """Per-dispatch rows (name, grid threads, duration ns, counter, value) of a rocprofv3 DB."""
+    import re
+    import sqlite3
+    c = sqlite3.connect(db)
+    out = []
+    try:
+        q = "select kernel_name, grid_size, duration, counter_name, value from counters_collection"
+        for name, grid, dur, cn, val in c.execute(q):
+            out.append((re.sub(r"\(.*", "", name).replace("lddmm::", ""), grid, dur, cn, val))
+    except sqlite3.Error:
+        pass
+    if not out:
+        q = "select name, grid_x*grid_y*grid_z, duration from kernels"
+        for name, grid, dur in c.execute(q):
+            out.append((re.sub(r"\(.*", "", name).replace("lddmm::", ""), grid, dur, None, None))
+    return out
+
+
+def _split_levels(items):
+    """Split the dispatches of one (kernel, grid) group at their largest duration gap
+    when durations span more than 4x (the same launch shape at two pyramid levels)."""
+    items = sorted(items, key=lambda r: r[0])
+    d = [r[0] for r in items]
+    if len(d) < 2 or d[-1] <= 4 * d[0]:
+        return [("", items)]
+    k = max(range(1, len(d)), key=lambda i: d[i] / max(d[i - 1], 1))
+    return [(" (short)", items[:k]), (" (long)", items[k:])]
+
+
+def summarize_profile(db, out_path, command):
+    """Write a text summary of a rocprofv3 DB: per (kernel, grid) calls, mean/min/max
+    duration and, for counter runs, mean counter value per dispatch (KiB for
+    FETCH_SIZE / WRITE_SIZE).  Returns {(kernel, grid, level tag): (calls, mean ns, mean counter)}."""
+    from collections import defaultdict
+    groups = defaultdict(list)
+    for name, grid, dur, cn, val in _kernel_rows(db):
+        groups[(name, grid, cn)].append((dur, val))
+    rows = []
+    for (name, grid, cn), items in groups.items():
+        for tag, part in _split_levels(items):
+            durs = [p[0] for p in part]
+            vals = [p[1] for p in part if p[1] is not None]
+            rows.append((name, grid, tag, cn, len(part), sum(durs), min(durs), max(durs),
+                         sum(vals) / len(vals) if vals else None))
+    tot = sum(r[5] for r in rows)
+    lines = [f"# rocprofv3 summary of: {command}", f"# database: {os.path.basename(db)}",
+             f"# total kernel time {tot / 1e6:.3f} ms over {sum(r[4] for r in rows)} dispatches",
+             "# grid = launch threads; (short)/(long): one launch shape at two problem sizes",
+             f"{'kernel':58s} {'grid':>18s} {'calls':>6s} {'avg_us':>9s} {'min_us':>8s} "
+             f"{'max_us':>8s} {'share':>6s} {'counter':>10s} {'avg/dispatch':>14s}"]
+    out = {}
+    for name, grid, tag, cn, n, s, mn, mx, cv in sorted(rows, key=lambda r: -r[5]):
+        cnt = f"{cv:14.1f}" if cv is not None else ""
+        lines.append(f"{name[:58]:58s} {str(grid) + tag:>18s} {n:6d} {s / n / 1e3:9.2f} "
+                     f"{mn / 1e3:8.2f} {mx / 1e3:8.2f} {100 * s / tot:5.1f}% "
+                     f"{(cn or ''):>10s} {cnt}")
+        out[(name, grid, tag)] = (n, s / n, cv)
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
+
+
+def library_sources_sha():
+    """SHA-256 of the HIP sources, to tell whether stored counters describe these kernels."""
+    import glob
+    import hashlib
+    hsh = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1605_02060_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            hsh.update(os.path.basename(p).encode())
+            hsh.update(f.read())
+    return hsh.hexdigest()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_atlas_finest.json")
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` at the finest level from the committed counter runs,
+    or None when the counters were taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != library_sources_sha():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,7 +208,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-out", default=None)
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("DB", "OUT", "COMMAND"),
+                    help="write a text summary of a rocprofv3 database and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(*args.summarize_profile)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the registration of one "
               "pair is a single-GPU workload in this build", file=sys.stderr)
@@ -197,7 +294,7 @@ def main():
         "data": "synthetic (seeded atlas-like template, sparse Poisson-labelled warped target)",
         "config": workload_config(),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dominant),
                      "kernel": f"k_{dominant}", "alg_bytes_per_voxel": ALG_BYTES[dominant],
                      "measured_on": "finest-level launches (280x160x240 grid) of the timed steps",
                      "avg_launch_ms": avg_ms, "launches": live["launches"],
