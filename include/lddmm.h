@@ -122,10 +122,24 @@ int32_t lddmm_trace_rows(const lddmm_params *params);
  * one.  v is upsampled (cell-centred trilinear) between levels.  The guard is
  * decided on the device; the call synchronises `stream` once at exit and
  * returns LDDMM_OK, a warning (LDDMM_WFOLD / LDDMM_WGUARD) or an error.
- * n_problems must be 1 for this entry point (batched form: lddmm_register_batched).
+ * With n_problems > 1 the call is lddmm_register_batched(p, n, params, NULL, stream)
+ * and returns the most severe status of the batch.
  */
 int lddmm_register(lddmm_problem *p, int32_t n_problems, const lddmm_params *params,
                    void *stream);
+
+/*
+ * Batched registration of n (1..32) independent problems of uneven size with one
+ * set of params (same T, levels, iterations, channel weights): every stage of
+ * every iteration is one kernel launch covering all problems (tiles of problem k
+ * follow those of problem k-1), so the launch count does not grow with n and
+ * small problems fill the GPU together.  Each problem keeps its own workspace,
+ * device-side guard and trace; results equal those of n single calls.
+ * status (host, n entries, may be NULL) receives each problem's status; the
+ * return value is the most severe one (an error before a warning).
+ */
+int lddmm_register_batched(lddmm_problem *p, int32_t n, const lddmm_params *params,
+                           int32_t *status, void *stream);
 
 /*
  * Energy of p->v on the single-level grid (n_levels ignored; h = grid.spacing):

@@ -58,12 +58,11 @@ __device__ double block1024_min(const double* p, int count, double* red) {
 // Reduce the energy of the evaluated velocity and take the guard decision.
 //  init = 1 : first evaluation of a level (row 0), no decision.
 //  mode GRAD / RETRY : the slot evaluated a trial in buffer 1 - base.
-__global__ __launch_bounds__(1024) void k_decide(State* st, const double* partR, int T,
-                                                 const double* partD, const double* partI,
-                                                 const double* partDet, int nfw, int nbw,
-                                                 int has_img, double dt, double h3,
-                                                 double inv_sigma2, int guard, double* trace,
-                                                 int init) {
+__device__ __forceinline__ void decide_body(State* st, const double* partR, int T,
+                                            const double* partD, const double* partI,
+                                            const double* partDet, int nfw, int nbw, int has_img,
+                                            double dt, double h3, double inv_sigma2, int guard,
+                                            double* trace, int init) {
   __shared__ double red[1024];
   const int mode = st->mode;
   if (mode == MODE_STOPPED) {
@@ -161,6 +160,27 @@ __global__ __launch_bounds__(1024) void k_decide(State* st, const double* partR,
   st->row += 1;
 }
 
+__global__ __launch_bounds__(1024) void k_decide(State* st, const double* partR, int T,
+                                                 const double* partD, const double* partI,
+                                                 const double* partDet, int nfw, int nbw,
+                                                 int has_img, double dt, double h3,
+                                                 double inv_sigma2, int guard, double* trace,
+                                                 int init) {
+  decide_body(st, partR, T, partD, partI, partDet, nfw, nbw, has_img, dt, h3, inv_sigma2, guard,
+              trace, init);
+}
+
+// One block per problem of a batch.
+__global__ __launch_bounds__(1024) void k_decide_batched(BatchRef br, int init) {
+  const DecideArgs& d = ((const PairTab*)br.tab[blockIdx.x])->dec[init];
+  decide_body(d.st, d.partR, d.T, d.partD, d.partI, d.partDet, d.nfw, d.nbw, d.has_img, d.dt, d.h3,
+              d.inv_sigma2, d.guard, d.trace, d.init);
+}
+
+void launch_decide_batched(const BatchRef& br, int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_decide_batched, dim3(br.np), dim3(1024), 0, s, br, init);
+}
+
 void launch_decide(State* st, const double* partR, int T, const double* partD, const double* partI,
                    const double* partDet, int nblk_fwd, int nblk_bwd, int has_img, double dt,
                    double h3, double inv_sigma2, int guard, double* trace, int init,
@@ -170,14 +190,28 @@ void launch_decide(State* st, const double* partR, int T, const double* partD, c
 }
 
 // After a rejection: trial <- (base + trial) / 2, i.e. v - eps g with the halved eps.
-__global__ __launch_bounds__(kBlock) void k_retry(float* vA, float* vB, long long count,
-                                                  const State* st) {
+__device__ __forceinline__ void retry_body(float* vA, float* vB, long long count, const State* st,
+                                           long long tile, long long ntiles) {
   if (st->mode != MODE_RETRY) return;
   const float* base = st->base ? vB : vA;
   float* trial = st->base ? vA : vB;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < count;
-       i += (long long)gridDim.x * kBlock)
+  for (long long i = tile * kBlock + threadIdx.x; i < count; i += ntiles * kBlock)
     trial[i] = 0.5f * (base[i] + trial[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_retry(float* vA, float* vB, long long count,
+                                                  const State* st) {
+  retry_body(vA, vB, count, st, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_retry_batched(BatchRef br) {
+  const int p = batch_pair(br, blockIdx.x);
+  const RetryArgs& r = ((const PairTab*)br.tab[p])->rty;
+  retry_body(r.vA, r.vB, r.count, r.st, blockIdx.x - br.off[p], br.off[p + 1] - br.off[p]);
+}
+
+void launch_retry_batched(const BatchRef& br, hipStream_t s) {
+  hipLaunchKernelGGL(k_retry_batched, dim3(br.off[br.np]), dim3(kBlock), 0, s, br);
 }
 
 void launch_retry(float* vA, float* vB, long long count, const State* st, hipStream_t s) {

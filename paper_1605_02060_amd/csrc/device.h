@@ -52,14 +52,16 @@ __device__ __forceinline__ float lerp_cell(const Cell& c, float v0, float v1, fl
 // round-robin (block b runs on XCD b mod 8), so the blocks of one XCD take one
 // contiguous eighth of the grid -- a slab of whole z-planes -- and stride through
 // it together, keeping stencil and gather neighbours of the current window in
-// that XCD's L2.  gridDim.x is a multiple of 8.
+// that XCD's L2.  `tile` is the block's index among the `ntiles` (a multiple of
+// 8) blocks of this problem; batched launches start every problem's tiles at a
+// multiple of 8, so tile mod 8 is still the XCD.
 struct XcdRange {
   uint32_t first, end, stride;
 };
 
-__device__ __forceinline__ XcdRange xcd_range(uint32_t n) {
-  const uint32_t xcd = blockIdx.x % kXCD, local = blockIdx.x / kXCD;
-  const uint32_t per = gridDim.x / kXCD;
+__device__ __forceinline__ XcdRange xcd_range(uint32_t n, uint32_t tile, uint32_t ntiles) {
+  const uint32_t xcd = tile % kXCD, local = tile / kXCD;
+  const uint32_t per = ntiles / kXCD;
   const uint32_t chunk = (n + kXCD - 1) / kXCD;
   const uint32_t beg = xcd * chunk;
   const uint32_t end = beg + chunk < n ? beg + chunk : n;
@@ -281,5 +283,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// Problem of block b in a batched launch (tile offsets are ascending).
+__device__ __forceinline__ int batch_pair(const BatchRef& br, int b) {
+  int p = 0;
+  while (p + 1 < br.np && b >= br.off[p + 1]) ++p;
+  return p;
+}
 
 }  // namespace lddmm

@@ -331,16 +331,19 @@ __device__ __forceinline__ bool gate(const State* st, int need_mode) {
 // After the DFT, for k < hx:  A[k] = (Z[k] + conj Z[-k]) / 2,  B[k] = (Z[k] - conj Z[-k]) / 2i.
 
 template <int EMAX>
-__global__ __launch_bounds__(kBlock) void k_fft_x_fwd(const float* __restrict__ b,
-                                                      float2* __restrict__ S, Geom g, FFTPlan p,
-                                                      const float2* __restrict__ tw, int ppb,
-                                                      const State* st, int need_mode) {
-  if (!gate(st, need_mode)) return;
+__device__ __forceinline__ void x_fwd_body(const FftPair& f, int block) {
+  if (!gate(f.st, f.need_mode)) return;
   extern __shared__ float2 sm[];
+  const float* __restrict__ b = f.b;
+  float2* __restrict__ S = f.S;
+  const Geom& g = f.g;
+  const FFTPlan& p = f.px;
+  const float2* __restrict__ tw = f.tw[0];
+  const int ppb = f.ppb;
   const int N = g.nx;
   const long long n = g.n;
   const int nrows = g.ny * g.nz;
-  const int pair0 = blockIdx.x * ppb;
+  const int pair0 = block * ppb;
   const int nl = 3 * ppb;
   const int tot = nl * N;
   float2 tmp[EMAX];
@@ -398,6 +401,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(const float* __restrict__ 
   }
 }
 
+template <int EMAX>
+__global__ __launch_bounds__(kBlock) void k_fft_x_fwd(FftPair f) {
+  x_fwd_body<EMAX>(f, blockIdx.x);
+}
+
+template <int EMAX>
+__global__ __launch_bounds__(kBlock) void k_fft_x_fwd_batched(BatchRef br) {
+  const int p = batch_pair(br, blockIdx.x);
+  x_fwd_body<EMAX>(((const PairTab*)br.tab[p])->fft, blockIdx.x - br.off[p]);
+}
+
 // Row pairs per block of the x passes and the register budget they need.
 static int pairs_per_block(int N, int* emax) {
   int ppb = kFFTElems / (3 * N);
@@ -406,24 +420,6 @@ static int pairs_per_block(int N, int* emax) {
   const int tot = 3 * ppb * N;
   *emax = tot <= kBlock * 8 ? 8 : (tot <= kBlock * 16 ? 16 : 32);
   return ppb;
-}
-
-void launch_fft_x_fwd(const float* b, float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
-                      const State* st, int need_mode, hipStream_t s) {
-  int emax;
-  const int ppb = pairs_per_block(g.nx, &emax);
-  const int npairs = (g.ny * g.nz + 1) / 2;
-  const int grid = (npairs + ppb - 1) / ppb;
-  const size_t lds = (size_t)3 * ppb * g.nx * sizeof(float2);
-  if (emax == 8)
-    hipLaunchKernelGGL(k_fft_x_fwd<8>, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb, st,
-                       need_mode);
-  else if (emax == 16)
-    hipLaunchKernelGGL(k_fft_x_fwd<16>, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb,
-                       st, need_mode);
-  else
-    hipLaunchKernelGGL(k_fft_x_fwd<32>, dim3(grid), dim3(kBlock), lds, s, b, S, g, p, tw, ppb,
-                       st, need_mode);
 }
 
 // ------------------------------------------------------ y and z passes ----
@@ -486,88 +482,76 @@ __device__ __forceinline__ void tile_store(const float2* sm, float2* __restrict_
 }
 
 template <int EMAX, bool INV>
-__global__ __launch_bounds__(kBlock) void k_fft_y(float2* __restrict__ S, Geom g, FFTPlan p,
-                                                  const float2* __restrict__ tw, int lgTX,
-                                                  const State* st, int need_mode) {
-  if (!gate(st, need_mode)) return;
+__device__ __forceinline__ void y_body(const FftPair& f, int bx, int bz_slab, int comp) {
+  if (!gate(f.st, f.need_mode)) return;
   extern __shared__ float2 sm[];
+  const Geom& g = f.g;
+  const int lgTX = f.lgTXy;
   const int N = g.ny, hx = g.hx, hs = g.hs, ls = N + 1;
   const int TX = 1 << lgTX;
-  const int kx0 = blockIdx.x * TX;
-  float2* base = S + (long long)blockIdx.z * g.nspec + (long long)blockIdx.y * g.ny * hs;
+  const int kx0 = bx * TX;
+  float2* base = f.S + (long long)comp * g.nspec + (long long)bz_slab * g.ny * hs;
   tile_load<EMAX, INV>(sm, base, lgTX, N, ls, hx, kx0, hs);
-  lds_fft<EMAX>(sm, ls, TX, p, tw);
+  lds_fft<EMAX>(sm, ls, TX, f.py, f.tw[1]);
   tile_store<INV>(sm, base, lgTX, N, ls, hx, kx0, hs);
 }
 
-void launch_fft_y(float2* S, const Geom& g, const FFTPlan& p, const float2* tw, int inverse,
-                  const State* st, int need_mode, hipStream_t s) {
-  int emax;
-  const int TX = tile_cols(g.ny, &emax);
-  dim3 grid((g.hx + TX - 1) / TX, g.nz, 3);
-  const size_t lds = (size_t)TX * (g.ny + 1) * sizeof(float2);
-#define LAUNCH_Y(E, I)                                                                          \
-  hipLaunchKernelGGL((k_fft_y<E, I>), grid, dim3(kBlock), lds, s, S, g, p, tw, ilog2(TX), st, \
-                     need_mode)
-  if (emax == 8) {
-    if (inverse) LAUNCH_Y(8, true); else LAUNCH_Y(8, false);
-  } else if (emax == 16) {
-    if (inverse) LAUNCH_Y(16, true); else LAUNCH_Y(16, false);
-  } else {
-    if (inverse) LAUNCH_Y(32, true); else LAUNCH_Y(32, false);
-  }
-#undef LAUNCH_Y
+template <int EMAX, bool INV>
+__global__ __launch_bounds__(kBlock) void k_fft_y(FftPair f) {
+  y_body<EMAX, INV>(f, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int EMAX, bool INV>
+__global__ __launch_bounds__(kBlock) void k_fft_y_batched(BatchRef br) {
+  const int p = batch_pair(br, blockIdx.x);
+  const FftPair& f = ((const PairTab*)br.tab[p])->fft;
+  const int t = blockIdx.x - br.off[p];
+  const int bx = t % f.nbx_y, r = t / f.nbx_y;
+  y_body<EMAX, INV>(f, bx, r % f.g.nz, r / f.g.nz);
 }
 
 template <int EMAX>
-__global__ __launch_bounds__(kBlock) void k_fft_z_K(float2* __restrict__ S, Geom g, FFTPlan p,
-                                                    const float2* __restrict__ tw, int lgTX,
-                                                    const double* __restrict__ lamx,
-                                                    const double* __restrict__ lamy,
-                                                    const double* __restrict__ lamz, double alpha,
-                                                    double gamma, const State* st, int need_mode) {
-  if (!gate(st, need_mode)) return;
+__device__ __forceinline__ void zK_body(const FftPair& f, int bx, int ky, int comp) {
+  if (!gate(f.st, f.need_mode)) return;
   extern __shared__ float2 sm[];
+  const Geom& g = f.g;
+  const int lgTX = f.lgTXz;
   const int N = g.nz, hx = g.hx, ls = N + 1;
   const int TX = 1 << lgTX;
-  const int kx0 = blockIdx.x * TX;
-  const int ky = blockIdx.y;
+  const int kx0 = bx * TX;
   const int zs = g.ny * g.hs;
-  float2* base = S + (long long)blockIdx.z * g.nspec + (long long)ky * g.hs;
+  float2* base = f.S + (long long)comp * g.nspec + (long long)ky * g.hs;
   tile_load<EMAX, false>(sm, base, lgTX, N, ls, hx, kx0, zs);
-  lds_fft<EMAX>(sm, ls, TX, p, tw);
+  lds_fft<EMAX>(sm, ls, TX, f.pz, f.tw[2]);
   const double inv_n = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
-  const double lyy = lamy[ky];
+  const double* __restrict__ lamx = f.lam[0];
+  const double* __restrict__ lamz = f.lam[2];
+  const double lyy = f.lam[1][ky];
   for (int e = threadIdx.x; e < TX * N; e += kBlock) {
     const int c = (int)fdiv((uint32_t)e, g.fz), kz = e - c * N;
     const int kx = kx0 + c < hx ? kx0 + c : 0;
-    const double lam = alpha * (lamx[kx] + lyy + lamz[kz]) + gamma;
+    const double lam = f.alpha * (lamx[kx] + lyy + lamz[kz]) + f.gamma;
     const float kh = (float)(inv_n / (lam * lam));
     const float2 v = sm[c * ls + kz];
     sm[c * ls + kz] = make_float2(v.x * kh, -v.y * kh);     // conj(K_hat X / |P|)
   }
   __syncthreads();
-  lds_fft<EMAX>(sm, ls, TX, p, tw);
+  lds_fft<EMAX>(sm, ls, TX, f.pz, f.tw[2]);
   tile_store<true>(sm, base, lgTX, N, ls, hx, kx0, zs);
 }
 
-void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
-                    const double* lamx, const double* lamy, const double* lamz, double alpha,
-                    double gamma, const State* st, int need_mode, hipStream_t s) {
-  int emax;
-  const int TX = tile_cols(g.nz, &emax);
-  dim3 grid((g.hx + TX - 1) / TX, g.ny, 3);
-  const size_t lds = (size_t)TX * (g.nz + 1) * sizeof(float2);
-#define LAUNCH_Z(E)                                                                             \
-  hipLaunchKernelGGL(k_fft_z_K<E>, grid, dim3(kBlock), lds, s, S, g, p, tw, ilog2(TX), lamx,  \
-                     lamy, lamz, alpha, gamma, st, need_mode)
-  if (emax == 8)
-    LAUNCH_Z(8);
-  else if (emax == 16)
-    LAUNCH_Z(16);
-  else
-    LAUNCH_Z(32);
-#undef LAUNCH_Z
+template <int EMAX>
+__global__ __launch_bounds__(kBlock) void k_fft_z_K(FftPair f) {
+  zK_body<EMAX>(f, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int EMAX>
+__global__ __launch_bounds__(kBlock) void k_fft_z_K_batched(BatchRef br) {
+  const int p = batch_pair(br, blockIdx.x);
+  const FftPair& f = ((const PairTab*)br.tab[p])->fft;
+  const int t = blockIdx.x - br.off[p];
+  const int bx = t % f.nbx_z, r = t / f.nbx_z;
+  zK_body<EMAX>(f, bx, r % f.g.ny, r / f.g.ny);
 }
 
 // ----------------------------------------------------- x inverse + update ----
@@ -576,16 +560,19 @@ void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw
 // invert, and split real / imaginary parts back into the two real lines.
 
 template <int EMAX>
-__global__ __launch_bounds__(kBlock) void k_fft_x_inv(const float2* __restrict__ S, Geom g,
-                                                      FFTPlan p, const float2* __restrict__ tw,
-                                                      int ppb, UpdArgs u) {
+__device__ __forceinline__ void x_inv_body(const FftPair& f, const UpdArgs& u, int block) {
   const State* st = u.st;
   if (!gate(st, u.need_mode)) return;
   extern __shared__ float2 sm[];
+  const float2* __restrict__ S = f.S;
+  const Geom& g = f.g;
+  const FFTPlan& p = f.px;
+  const float2* __restrict__ tw = f.tw[0];
+  const int ppb = f.ppb;
   const int N = g.nx, hx = g.hx, hs = g.hs;
   const long long n = g.n;
   const int nrows = g.ny * g.nz;
-  const int pair0 = blockIdx.x * ppb;
+  const int pair0 = block * ppb;
   const int nl = 3 * ppb;
   const int tot = nl * N;
   float2 tA[EMAX], tB[EMAX];
@@ -667,19 +654,119 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv(const float2* __restrict__
   }
 }
 
-void launch_fft_x_inv(const float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
-                      const UpdArgs& u, hipStream_t s) {
-  int emax;
-  const int ppb = pairs_per_block(g.nx, &emax);
-  const int npairs = (g.ny * g.nz + 1) / 2;
-  const int grid = (npairs + ppb - 1) / ppb;
-  const size_t lds = (size_t)3 * ppb * g.nx * sizeof(float2);
-  if (emax == 8)
-    hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
-  else if (emax == 16)
-    hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
+template <int EMAX>
+__global__ __launch_bounds__(kBlock) void k_fft_x_inv(FftPair f, UpdArgs u) {
+  x_inv_body<EMAX>(f, u, blockIdx.x);
+}
+
+template <int EMAX>
+__global__ __launch_bounds__(kBlock) void k_fft_x_inv_batched(BatchRef br, int j) {
+  const int p = batch_pair(br, blockIdx.x);
+  const PairTab* t = (const PairTab*)br.tab[p];
+  x_inv_body<EMAX>(t->fft, t->upd[j], blockIdx.x - br.off[p]);
+}
+
+// ------------------------------------------------------------- launchers ----
+
+// Fill the per-problem tile geometry of the five passes.
+void fft_tiles(FftPair& f, FftLaunch* L) {
+  int ex, ey, ez;
+  f.ppb = pairs_per_block(f.g.nx, &ex);
+  const int ty = tile_cols(f.g.ny, &ey), tz = tile_cols(f.g.nz, &ez);
+  f.lgTXy = ilog2(ty);
+  f.lgTXz = ilog2(tz);
+  f.nbx_y = (f.g.hx + ty - 1) / ty;
+  f.nbx_z = (f.g.hx + tz - 1) / tz;
+  L->x_tiles = ((f.g.ny * f.g.nz + 1) / 2 + f.ppb - 1) / f.ppb;
+  L->y_tiles = f.nbx_y * f.g.nz * 3;
+  L->z_tiles = f.nbx_z * f.g.ny * 3;
+  L->ex = ex;
+  L->ey = ey;
+  L->ez = ez;
+  L->x_lds = (size_t)3 * f.ppb * f.g.nx * sizeof(float2);
+  L->y_lds = (size_t)ty * (f.g.ny + 1) * sizeof(float2);
+  L->z_lds = (size_t)tz * (f.g.nz + 1) * sizeof(float2);
+}
+
+#define EMAX_SWITCH(E, CALL8, CALL16, CALL32) \
+  do {                                        \
+    if ((E) <= 8) CALL8;                      \
+    else if ((E) <= 16) CALL16;               \
+    else CALL32;                              \
+  } while (0)
+
+void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s) {
+  EMAX_SWITCH(L.ex,
+    hipLaunchKernelGGL(k_fft_x_fwd<8>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f),
+    hipLaunchKernelGGL(k_fft_x_fwd<16>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f),
+    hipLaunchKernelGGL(k_fft_x_fwd<32>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f));
+}
+
+void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t s) {
+  const dim3 grid(f.nbx_y, f.g.nz, 3);
+  if (inverse)
+    EMAX_SWITCH(L.ey,
+      hipLaunchKernelGGL((k_fft_y<8, true>), grid, dim3(kBlock), L.y_lds, s, f),
+      hipLaunchKernelGGL((k_fft_y<16, true>), grid, dim3(kBlock), L.y_lds, s, f),
+      hipLaunchKernelGGL((k_fft_y<32, true>), grid, dim3(kBlock), L.y_lds, s, f));
   else
-    hipLaunchKernelGGL(k_fft_x_inv<32>, dim3(grid), dim3(kBlock), lds, s, S, g, p, tw, ppb, u);
+    EMAX_SWITCH(L.ey,
+      hipLaunchKernelGGL((k_fft_y<8, false>), grid, dim3(kBlock), L.y_lds, s, f),
+      hipLaunchKernelGGL((k_fft_y<16, false>), grid, dim3(kBlock), L.y_lds, s, f),
+      hipLaunchKernelGGL((k_fft_y<32, false>), grid, dim3(kBlock), L.y_lds, s, f));
+}
+
+void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s) {
+  const dim3 grid(f.nbx_z, f.g.ny, 3);
+  EMAX_SWITCH(L.ez,
+    hipLaunchKernelGGL(k_fft_z_K<8>, grid, dim3(kBlock), L.z_lds, s, f),
+    hipLaunchKernelGGL(k_fft_z_K<16>, grid, dim3(kBlock), L.z_lds, s, f),
+    hipLaunchKernelGGL(k_fft_z_K<32>, grid, dim3(kBlock), L.z_lds, s, f));
+}
+
+void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hipStream_t s) {
+  EMAX_SWITCH(L.ex,
+    hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u),
+    hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u),
+    hipLaunchKernelGGL(k_fft_x_inv<32>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u));
+}
+
+// Batched passes: every problem of the batch in one launch (register budget and
+// LDS of the most demanding problem).
+void launch_fft_batched(int pass, const BatchRef& br, int emax, size_t lds, int j, hipStream_t s) {
+  const dim3 grid(br.off[br.np]);
+  switch (pass) {
+    case 0:
+      EMAX_SWITCH(emax,
+        hipLaunchKernelGGL(k_fft_x_fwd_batched<8>, grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL(k_fft_x_fwd_batched<16>, grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL(k_fft_x_fwd_batched<32>, grid, dim3(kBlock), lds, s, br));
+      break;
+    case 1:
+      EMAX_SWITCH(emax,
+        hipLaunchKernelGGL((k_fft_y_batched<8, false>), grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL((k_fft_y_batched<16, false>), grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL((k_fft_y_batched<32, false>), grid, dim3(kBlock), lds, s, br));
+      break;
+    case 2:
+      EMAX_SWITCH(emax,
+        hipLaunchKernelGGL(k_fft_z_K_batched<8>, grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL(k_fft_z_K_batched<16>, grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL(k_fft_z_K_batched<32>, grid, dim3(kBlock), lds, s, br));
+      break;
+    case 3:
+      EMAX_SWITCH(emax,
+        hipLaunchKernelGGL((k_fft_y_batched<8, true>), grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL((k_fft_y_batched<16, true>), grid, dim3(kBlock), lds, s, br),
+        hipLaunchKernelGGL((k_fft_y_batched<32, true>), grid, dim3(kBlock), lds, s, br));
+      break;
+    default:
+      EMAX_SWITCH(emax,
+        hipLaunchKernelGGL(k_fft_x_inv_batched<8>, grid, dim3(kBlock), lds, s, br, j),
+        hipLaunchKernelGGL(k_fft_x_inv_batched<16>, grid, dim3(kBlock), lds, s, br, j),
+        hipLaunchKernelGGL(k_fft_x_inv_batched<32>, grid, dim3(kBlock), lds, s, br, j));
+      break;
+  }
 }
 
 }  // namespace lddmm

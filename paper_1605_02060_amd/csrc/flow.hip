@@ -108,7 +108,7 @@ void launch_up2(const float* src, const Geom& coarse, float* dst, const Geom& fi
 // ---------------------------------------------------------- forward sweep ----
 
 template <int NC, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
+__device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, uint32_t ntiles) {
   const State* st = a.st;
   if (st->mode == MODE_STOPPED) return;
   const Geom g = a.g;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
   const float dt = a.dt, ih = g.inv_h;
   const float c2 = a.alpha * ih * ih;
   double accR = 0.0, accD = 0.0, accI = 0.0;
-  const XcdRange rg = xcd_range(n);
+  const XcdRange rg = xcd_range(n, tile, ntiles);
   for (uint32_t i = rg.first; i < rg.end; i += rg.stride) {
     int x, y, z;
     vcoord(g, i, x, y, z);
@@ -176,15 +176,28 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
     }
   }
   const double sR = block_sum(accR);
-  if (threadIdx.x == 0) a.partR[blockIdx.x] = sR;
+  if (threadIdx.x == 0) a.partR[tile] = sR;
   if (LAST) {
     const double sD = block_sum(accD);
     const double sI = block_sum(accI);
     if (threadIdx.x == 0) {
-      a.partD[blockIdx.x] = sD;
-      a.partI[blockIdx.x] = sI;
+      a.partD[tile] = sD;
+      a.partI[tile] = sI;
     }
   }
+}
+
+template <int NC, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
+  forward_body<NC, FIRST, LAST>(a, blockIdx.x, gridDim.x);
+}
+
+// One launch for every problem of a batch: block b runs tile b - off[p] of problem p.
+template <int NC, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) {
+  const int p = batch_pair(br, blockIdx.x);
+  const PairTab* t = (const PairTab*)br.tab[p];
+  forward_body<NC, FIRST, LAST>(t->fwd[j], blockIdx.x - br.off[p], br.off[p + 1] - br.off[p]);
 }
 
 template <int NC>
@@ -211,7 +224,7 @@ void launch_forward(const FwdArgs& a, hipStream_t s) {
 // --------------------------------------------------------- backward sweep ----
 
 template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
-__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
+__device__ __forceinline__ void backward_body(const BwdArgs& a, uint32_t tile, uint32_t ntiles) {
   const State* st = a.st;
   if (a.need_mode >= 0 && st->mode != a.need_mode) return;
   const Geom g = a.g;
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
     JJ[c] = rsrc(a.J0t + (long long)c * a.cstride, n);
   }
   double mind = 1e300;
-  const XcdRange rg = xcd_range(n);
+  const XcdRange rg = xcd_range(n, tile, ntiles);
   for (uint32_t i = rg.first; i < rg.end; i += rg.stride) {
     int x, y, z;
     vcoord(g, i, x, y, z);
@@ -286,8 +299,21 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
   }
   if (HAS_B) {
     const double m = block_min(mind);
-    if (threadIdx.x == 0) a.partDet[blockIdx.x] = m;
+    if (threadIdx.x == 0) a.partDet[tile] = m;
   }
+}
+
+template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
+__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
+  backward_body<NC, HAS_U, UZERO, HAS_B>(a, blockIdx.x, gridDim.x);
+}
+
+template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
+__global__ __launch_bounds__(kBlock) void k_backward_batched(BatchRef br, int slot) {
+  const int p = batch_pair(br, blockIdx.x);
+  const PairTab* t = (const PairTab*)br.tab[p];
+  backward_body<NC, HAS_U, UZERO, HAS_B>(t->bwd[slot], blockIdx.x - br.off[p],
+                                         br.off[p + 1] - br.off[p]);
 }
 
 template <int NC>
@@ -309,6 +335,42 @@ void launch_backward(const BwdArgs& a, hipStream_t s) {
     bwd_dispatch<2>(a, s);
   else
     bwd_dispatch<1>(a, s);
+}
+
+// Batched sweeps: step j of every problem (same T, same channel count).
+void launch_forward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s) {
+  const bool first = (j == 0), last = (j == T - 1);
+  const dim3 grid(br.off[br.np]);
+#define FWDB(NC, F, L) hipLaunchKernelGGL((k_forward_batched<NC, F, L>), grid, dim3(kBlock), 0, s, br, j)
+  if (nch == 2) {
+    if (first && last) FWDB(2, true, true); else if (first) FWDB(2, true, false);
+    else if (last) FWDB(2, false, true); else FWDB(2, false, false);
+  } else {
+    if (first && last) FWDB(1, true, true); else if (first) FWDB(1, true, false);
+    else if (last) FWDB(1, false, true); else FWDB(1, false, false);
+  }
+#undef FWDB
+}
+
+// slot = j + 1 (the table holds the T + 1 backward launches, j = T-1 .. -1)
+void launch_backward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s) {
+  const bool hu = j >= 0, uz = (j == T - 1), hb = (j + 1 <= T - 1);
+  const dim3 grid(br.off[br.np]);
+  const int slot = j + 1;
+#define BWDB(NC, A, B, C) \
+  hipLaunchKernelGGL((k_backward_batched<NC, A, B, C>), grid, dim3(kBlock), 0, s, br, slot)
+  if (nch == 2) {
+    if (hu && uz && !hb) BWDB(2, true, true, false);
+    else if (hu && !uz && hb) BWDB(2, true, false, true);
+    else if (hu && !uz && !hb) BWDB(2, true, false, false);
+    else if (!hu && hb) BWDB(2, false, false, true);
+  } else {
+    if (hu && uz && !hb) BWDB(1, true, true, false);
+    else if (hu && !uz && hb) BWDB(1, true, false, true);
+    else if (hu && !uz && !hb) BWDB(1, true, false, false);
+    else if (!hu && hb) BWDB(1, false, false, true);
+  }
+#undef BWDB
 }
 
 // ------------------------------------------------------------ utilities ----

@@ -134,6 +134,69 @@ struct UpdArgs {
   int need_mode;
 };
 
+// ------------------------------------------------------------- FFT passes --
+
+// One problem's K smoothing: geometry, plans, tables, buffers and tiles.
+struct FftPair {
+  Geom g;
+  FFTPlan px, py, pz;
+  const float2* tw[3];     // twiddles per axis
+  const double* lam[3];    // Laplacian symbol per axis
+  double alpha, gamma;
+  const float* b;          // body force [3][n]
+  float2* S;               // half spectrum [3][nspec]
+  int ppb;                 // x passes: row pairs per block
+  int lgTXy, nbx_y;        // y pass: log2 tile width, tiles along kx
+  int lgTXz, nbx_z;        // z pass
+  const State* st;
+  int need_mode;
+};
+
+// Launch shape of the five passes of one problem.
+struct FftLaunch {
+  int x_tiles, y_tiles, z_tiles;
+  int ex, ey, ez;          // per-thread register budget (8, 16 or 32 values)
+  size_t x_lds, y_lds, z_lds;
+};
+
+// ---------------------------------------------------------------- batching --
+
+constexpr int kMaxBatch = 32;     // problems per batched launch
+constexpr int kMaxT = 64;         // equals LDDMM_MAX_T
+
+// Tile offsets of one batched launch: problem p owns blocks [off[p], off[p+1]).
+struct BatchRef {
+  int np;
+  int off[kMaxBatch + 1];
+  const void* tab[kMaxBatch];     // device PairTab of each problem
+};
+
+struct DecideArgs {
+  State* st;
+  const double *partR, *partD, *partI, *partDet;
+  int T, nfw, nbw, has_img, guard, init;
+  double dt, h3, inv_sigma2;
+  double* trace;
+};
+
+struct RetryArgs {
+  float* vA;
+  float* vB;
+  long long count;
+  const State* st;
+};
+
+// Every launch argument of one problem at the current level, kept in device
+// memory so one kernel can serve all problems of a batch.
+struct PairTab {
+  FwdArgs fwd[kMaxT];
+  BwdArgs bwd[kMaxT + 1];   // slot j + 1 for backward launch j = -1 .. T-1
+  UpdArgs upd[kMaxT];
+  FftPair fft;
+  DecideArgs dec[2];        // [0]: after a trial, [1]: first evaluation of a level
+  RetryArgs rty;
+};
+
 // --------------------------------------------------------------- launchers --
 // flow.hip
 void launch_pad(const float* src, int Nx, int Ny, int Nz, float* dst, const Geom& g,
@@ -146,6 +209,8 @@ int reduce_grid(long long n);
 void set_sweep_blocks(int blocks);
 void launch_forward(const FwdArgs& a, hipStream_t s);
 void launch_backward(const BwdArgs& a, hipStream_t s);
+void launch_forward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);
+void launch_backward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);
 void launch_crop3(const float* u, const Geom& g, int Nx, int Ny, int Nz, float* out,
                   hipStream_t s);
 void launch_apply(const float* u, int Nx, int Ny, int Nz, float inv_h, const void* src,
@@ -159,15 +224,12 @@ void launch_copy(const float* src, float* dst, long long n, hipStream_t s);
 bool make_plan(int n, FFTPlan* p);
 void launch_twiddles(float2* tw, int n, hipStream_t s);
 void launch_lambda(double* lam, int n, double h, hipStream_t s);
-void launch_fft_x_fwd(const float* b, float2* S, const Geom& g, const FFTPlan& p,
-                      const float2* tw, const State* st, int need_mode, hipStream_t s);
-void launch_fft_y(float2* S, const Geom& g, const FFTPlan& p, const float2* tw, int inverse,
-                  const State* st, int need_mode, hipStream_t s);
-void launch_fft_z_K(float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
-                    const double* lamx, const double* lamy, const double* lamz, double alpha,
-                    double gamma, const State* st, int need_mode, hipStream_t s);
-void launch_fft_x_inv(const float2* S, const Geom& g, const FFTPlan& p, const float2* tw,
-                      const UpdArgs& u, hipStream_t s);
+void fft_tiles(FftPair& f, FftLaunch* L);
+void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s);
+void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t s);
+void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s);
+void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hipStream_t s);
+void launch_fft_batched(int pass, const BatchRef& br, int emax, size_t lds, int j, hipStream_t s);
 
 // grad.hip
 struct GradArgs {
@@ -199,6 +261,8 @@ void launch_decide(State* st, const double* partR, int T, const double* partD,
                    int has_img, double dt, double h3, double inv_sigma2, int guard,
                    double* trace, int init, hipStream_t s);
 void launch_retry(float* vA, float* vB, long long count, const State* st, hipStream_t s);
+void launch_decide_batched(const BatchRef& br, int init, hipStream_t s);
+void launch_retry_batched(const BatchRef& br, hipStream_t s);
 void launch_energy_out(const State* st, double* out4, hipStream_t s);
 
 }  // namespace lddmm

@@ -2,6 +2,7 @@
 // geometry, workspace layout, and the launch sequence of the descent.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -116,7 +117,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t state, partR, partD, partI, partDet, trace, tw[3], lam[3];
-  size_t J0, J1, v0, v1, u0, u1, J0t, r, b, S, ub, misc, total;
+  size_t J0, J1, v0, v1, u0, u1, J0t, r, b, S, ub, misc, ptab, total;
   size_t Joff[LDDMM_MAX_LEVELS];   // per-level offsets (floats) inside J0 / J1
   int n_u0;                         // u0 slots
 };
@@ -256,6 +257,7 @@ static Layout make_layout(const Config& c) {
   o.S = take(sizeof(float2) * 3 * (size_t)gf.nspec);
   o.ub = take(sizeof(float) * 3 * n * 2);
   o.misc = take(sizeof(int) * 64);
+  o.ptab = take(sizeof(PairTab));
   o.total = align_up(off);
   return o;
 }
@@ -271,6 +273,7 @@ struct Ctx {
   double* lam[3];
   float *J0, *J1, *v[2], *u0, *u1, *J0t, *r, *b, *ub;
   int* misc;
+  PairTab* ptab;
   float2* S;
   double alpha, gamma, sigma;
   int guard;
@@ -301,6 +304,7 @@ static void bind(Ctx& c, void* ws) {
   c.S = (float2*)(c.ws + o.S);
   c.ub = (float*)(c.ws + o.ub);
   c.misc = (int*)(c.ws + o.misc);
+  c.ptab = (PairTab*)(c.ws + o.ptab);
 }
 
 static void level_tables(Ctx& c, const Level& L, hipStream_t s) {
@@ -365,30 +369,52 @@ static float* u0_final(Ctx& c, int li, bool keep_all) {
   return c.u0 + (long long)(keep_all ? T : (T & 1)) * 3 * n;
 }
 
+// FFT pass parameters of one problem at one level.
+static FftPair make_fft(Ctx& c, int li, int need_mode, FftLaunch* L) {
+  FftPair f{};
+  const Level& lv = c.cfg.lv[li];
+  f.g = lv.g;
+  f.px = lv.px;
+  f.py = lv.py;
+  f.pz = lv.pz;
+  for (int d = 0; d < 3; ++d) {
+    f.tw[d] = c.tw[d];
+    f.lam[d] = c.lam[d];
+  }
+  f.alpha = c.alpha;
+  f.gamma = c.gamma;
+  f.b = c.b;
+  f.S = c.S;
+  f.st = c.st;
+  f.need_mode = need_mode;
+  fft_tiles(f, L);
+  return f;
+}
+
 // K smoothing of c.b followed by the x-inverse epilogue.
 static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, hipStream_t s) {
-  const Level& L = c.cfg.lv[li];
-  const long long n = L.g.n;
+  const long long n = c.cfg.lv[li].g.n;
+  FftLaunch L;
+  const FftPair f = make_fft(c, li, need_mode, &L);
   {
     ProfScope ps(LDDMM_PROF_FFT_X, n, s);
-    launch_fft_x_fwd(c.b, c.S, L.g, L.px, c.tw[0], c.st, need_mode, s);
+    launch_fft_x_fwd(f, L, s);
   }
   {
     ProfScope ps(LDDMM_PROF_FFT_Y, n, s);
-    launch_fft_y(c.S, L.g, L.py, c.tw[1], 0, c.st, need_mode, s);
+    launch_fft_y(f, L, 0, s);
   }
   {
     ProfScope ps(LDDMM_PROF_FFT_ZK, n, s);
-    launch_fft_z_K(c.S, L.g, L.pz, c.tw[2], c.lam[0], c.lam[1], c.lam[2], c.alpha, c.gamma,
-                   c.st, need_mode, s);
+    launch_fft_z_K(f, L, s);
   }
   {
     ProfScope ps(LDDMM_PROF_FFT_YINV, n, s);
-    launch_fft_y(c.S, L.g, L.py, c.tw[1], 1, c.st, need_mode, s);
+    launch_fft_y(f, L, 1, s);
   }
   {
     ProfScope ps(LDDMM_PROF_FFT_XINV, n, s);
-    launch_fft_x_inv(c.S, L.g, L.px, c.tw[0], u, s);
+    launch_fft_x_inv(f, L, u, s);
   }
 }
 
@@ -636,6 +662,7 @@ int32_t lddmm_trace_rows(const lddmm_params* params) {
 }
 
 int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm, void* stream) {
+  if (n_problems > 1) return lddmm_register_batched(p, n_problems, prm, nullptr, stream);
   if (n_problems != 1) return LDDMM_EINVAL;
   Ctx c{};
   int rc = prepare(c, p, prm, 1);
@@ -712,6 +739,283 @@ int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm
   if (hs.min_det_all <= 0.0) return LDDMM_WFOLD;
   return LDDMM_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------- batched ----
+
+namespace lddmm {
+
+// Launch arguments of every kernel of one problem at level li, as the single
+// problem path builds them (ping-pong map slots, per-step partial buffers).
+static void build_pairtab(Ctx& c, int li, PairTab* t) {
+  const Config& k = c.cfg;
+  const Level& L = k.lv[li];
+  const long long n = L.g.n;
+  std::memset((void*)t, 0, sizeof(PairTab));
+  for (int j = 0; j < k.T; ++j) {
+    FwdArgs& a = t->fwd[j];
+    a.g = L.g;
+    a.vA = c.v[0];
+    a.vB = c.v[1];
+    a.j = j;
+    a.T = k.T;
+    a.dt = 1.0f / (float)k.T;
+    a.alpha = (float)c.alpha;
+    a.gamma = (float)c.gamma;
+    a.u_cur = c.u0 + (long long)(j & 1) * 3 * n;
+    a.u_next = c.u0 + (long long)((j + 1) & 1) * 3 * n;
+    a.J0 = c.J0 + c.lay.Joff[li];
+    a.J1 = c.J1 + c.lay.Joff[li];
+    a.nch = k.nch;
+    a.ch[0] = k.ch[0];
+    a.ch[1] = k.nch > 1 ? k.ch[1] : k.ch[0];
+    a.w[0] = k.w[0];
+    a.w[1] = k.nch > 1 ? k.w[1] : 0.f;
+    a.img_ch = k.img_ch;
+    a.img_weighted = k.img_weighted;
+    a.img_slot = k.img_slot;
+    a.J0t_next = c.J0t + (long long)(j + 1 < k.T ? j + 1 : 0) * k.nch * n;
+    a.r = c.r;
+    a.partR = c.partR + (long long)j * kPartMax;
+    a.partD = c.partD;
+    a.partI = c.partI;
+    a.st = c.st;
+  }
+  for (int j = k.T - 1; j >= -1; --j) {
+    BwdArgs& a = t->bwd[j + 1];
+    a.g = L.g;
+    a.vA = c.v[0];
+    a.vB = c.v[1];
+    a.vfix = nullptr;
+    a.T = k.T;
+    a.dt = 1.0f / (float)k.T;
+    a.j = j;
+    a.u_next = (j == k.T - 1) ? nullptr : c.u1 + (long long)((j + 1) & 1) * 3 * n;
+    a.u_cur = j >= 0 ? c.u1 + (long long)(j & 1) * 3 * n : nullptr;
+    const int jb = j + 1;
+    a.jb = jb <= k.T - 1 ? jb : -1;
+    if (a.jb == 0) {
+      a.J0t = c.J0 + c.lay.Joff[li] + (long long)k.ch[0] * n;
+      a.cstride = k.nch > 1 ? (long long)(k.ch[1] - k.ch[0]) * n : n;
+    } else {
+      a.J0t = c.J0t + (long long)(a.jb >= 0 ? a.jb : 0) * k.nch * n;
+      a.cstride = n;
+    }
+    a.r = c.r;
+    a.nch = k.nch;
+    a.w[0] = k.w[0];
+    a.w[1] = k.nch > 1 ? k.w[1] : 0.f;
+    a.coef = (float)(2.0 / (c.sigma * c.sigma));
+    a.b = c.b;
+    a.partDet = c.partDet + (long long)(a.jb >= 0 ? a.jb : 0) * kPartMax;
+    a.st = c.st;
+    a.need_mode = MODE_GRAD;
+  }
+  for (int j = 0; j < k.T; ++j) {
+    UpdArgs& u = t->upd[j];
+    u.kind = UPD_STEP;
+    u.j = j;
+    u.vA = c.v[0];
+    u.vB = c.v[1];
+    u.st = c.st;
+    u.need_mode = MODE_GRAD;
+  }
+  FftLaunch Lf;
+  t->fft = make_fft(c, li, MODE_GRAD, &Lf);
+  const int nb = reduce_grid(n);
+  const double h = (double)L.g.h;
+  for (int init = 0; init < 2; ++init) {
+    DecideArgs& d = t->dec[init];
+    d.st = c.st;
+    d.partR = c.partR;
+    d.partD = c.partD;
+    d.partI = c.partI;
+    d.partDet = c.partDet;
+    d.T = k.T;
+    d.nfw = nb;
+    d.nbw = nb;
+    d.has_img = k.C > 1;
+    d.guard = c.guard;
+    d.init = init;
+    d.dt = 1.0 / k.T;
+    d.h3 = h * h * h;
+    d.inv_sigma2 = 1.0 / (c.sigma * c.sigma);
+    d.trace = c.trace;
+  }
+  t->rty.vA = c.v[0];
+  t->rty.vB = c.v[1];
+  t->rty.count = 3 * n * k.T;
+  t->rty.st = c.st;
+}
+
+struct BatchPlan {
+  BatchRef fwd, bwd, fx, fy, fz, fxi, dec, rty;
+  int ex, ey, ez;
+  size_t xl, yl, zl;
+};
+
+static void batch_offsets(BatchRef& br, int np, const int* tiles, PairTab* const* tabs) {
+  br.np = np;
+  br.off[0] = 0;
+  for (int p = 0; p < np; ++p) {
+    br.off[p + 1] = br.off[p] + tiles[p];
+    br.tab[p] = tabs[p];
+  }
+}
+
+}  // namespace lddmm
+
+extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const lddmm_params* prm,
+                                      int32_t* status, void* stream) {
+  if (!probs || !prm || n < 1 || n > kMaxBatch) return LDDMM_EINVAL;
+  std::vector<Ctx> cs(n);
+  for (int p = 0; p < n; ++p) {
+    int rc = prepare(cs[p], &probs[p], prm, 1);
+    if (rc) return rc;
+  }
+  for (int p = 1; p < n; ++p)
+    if (cs[p].cfg.nch != cs[0].cfg.nch || cs[p].cfg.L != cs[0].cfg.L) return LDDMM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipGetLastError();
+  const int T = cs[0].cfg.T, L = cs[0].cfg.L, nch = cs[0].cfg.nch;
+  std::vector<PairTab> host_tabs((size_t)n * L);
+  for (int p = 0; p < n; ++p) {
+    Ctx& c = cs[p];
+    const Config& k = c.cfg;
+    const int top = k.L - 1;
+    setup_images(c, &probs[p], s);
+    const float* src = probs[p].v;
+    int dst = 1;
+    for (int li = top - 1; li >= 0; --li) {
+      launch_down2(src, k.lv[li + 1].g, c.v[dst], k.lv[li].g, 3 * k.T, s);
+      src = c.v[dst];
+      dst ^= 1;
+    }
+    launch_copy(src, c.v[0], 3 * k.lv[0].g.n * k.T, s);
+    launch_level_begin(c.st, prm->step, 0, s);
+  }
+  std::vector<PairTab*> dtabs(n);
+  for (int p = 0; p < n; ++p) dtabs[p] = cs[p].ptab;
+  for (int li = 0; li < L; ++li) {
+    BatchPlan bp{};
+    std::vector<int> tf(n), tx(n), ty(n), tz(n), tr(n), one(n, 1);
+    for (int p = 0; p < n; ++p) {
+      Ctx& c = cs[p];
+      const Config& k = c.cfg;
+      const Level& lv = k.lv[li];
+      if (li > 0) {
+        canonicalize(c, 3 * k.lv[li - 1].g.n * k.T, s);
+        launch_up2(c.v[0], k.lv[li - 1].g, c.v[1], lv.g, 3 * k.T, s);
+        launch_copy(c.v[1], c.v[0], 3 * lv.g.n * k.T, s);
+        launch_level_begin(c.st, prm->step, 1, s);
+      }
+      level_tables(c, lv, s);
+      PairTab* ht = &host_tabs[(size_t)li * n + p];
+      build_pairtab(c, li, ht);
+      if (hipMemcpyAsync(c.ptab, ht, sizeof(PairTab), hipMemcpyHostToDevice, s) != hipSuccess)
+        return LDDMM_EHIP;
+      FftLaunch Lf;
+      FftPair tmp = make_fft(c, li, MODE_GRAD, &Lf);
+      (void)tmp;
+      tf[p] = reduce_grid(lv.g.n);
+      tx[p] = Lf.x_tiles;
+      ty[p] = Lf.y_tiles;
+      tz[p] = Lf.z_tiles;
+      long long rb = (3 * lv.g.n * k.T + kBlock - 1) / kBlock;
+      tr[p] = (int)(rb > 65536 ? 65536 : rb);
+      bp.ex = std::max(bp.ex, Lf.ex);
+      bp.ey = std::max(bp.ey, Lf.ey);
+      bp.ez = std::max(bp.ez, Lf.ez);
+      bp.xl = std::max(bp.xl, Lf.x_lds);
+      bp.yl = std::max(bp.yl, Lf.y_lds);
+      bp.zl = std::max(bp.zl, Lf.z_lds);
+    }
+    batch_offsets(bp.fwd, n, tf.data(), dtabs.data());
+    bp.bwd = bp.fwd;
+    batch_offsets(bp.fx, n, tx.data(), dtabs.data());
+    bp.fxi = bp.fx;
+    batch_offsets(bp.fy, n, ty.data(), dtabs.data());
+    batch_offsets(bp.fz, n, tz.data(), dtabs.data());
+    batch_offsets(bp.dec, n, one.data(), dtabs.data());
+    batch_offsets(bp.rty, n, tr.data(), dtabs.data());
+    auto forward_all = [&]() {
+      for (int j = 0; j < T; ++j) launch_forward_batched(bp.fwd, j, T, nch, s);
+    };
+    forward_all();
+    launch_decide_batched(bp.dec, 1, s);
+    for (int it = 0; it < prm->iters[li]; ++it) {
+      for (int j = T - 1; j >= -1; --j) {
+        launch_backward_batched(bp.bwd, j, T, nch, s);
+        const int jb = j + 1;
+        if (jb <= T - 1) {
+          launch_fft_batched(0, bp.fx, bp.ex, bp.xl, jb, s);
+          launch_fft_batched(1, bp.fy, bp.ey, bp.yl, jb, s);
+          launch_fft_batched(2, bp.fz, bp.ez, bp.zl, jb, s);
+          launch_fft_batched(3, bp.fy, bp.ey, bp.yl, jb, s);
+          launch_fft_batched(4, bp.fxi, bp.ex, bp.xl, jb, s);
+        }
+      }
+      launch_retry_batched(bp.rty, s);
+      forward_all();
+      launch_decide_batched(bp.dec, 0, s);
+    }
+  }
+  // outputs of every problem from its final iterate
+  for (int p = 0; p < n; ++p) {
+    Ctx& c = cs[p];
+    const Config& k = c.cfg;
+    const int top = k.L - 1;
+    const long long nf = k.lv[top].g.n;
+    lddmm_problem* pr = &probs[p];
+    canonicalize(c, 3 * nf * k.T, s);
+    launch_copy(c.v[0], pr->v, 3 * nf * k.T, s);
+    hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, c.st, 0, (int)MODE_INIT);
+    if (pr->phi10) {
+      forward_sweep(c, top, c.v[0], c.v[1], false, s);
+      launch_crop3(u0_final(c, top, false), k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1],
+                   k.lv[top].N[2], pr->phi10, s);
+    }
+    if (pr->phi01) {
+      backward_sweep(c, top, c.v[0], c.v[1], c.v[0], false, UPD_STEP, nullptr, -1, s);
+      launch_crop3(c.u1, k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1], k.lv[top].N[2], pr->phi01,
+                   s);
+    }
+    if (pr->trace) {
+      const int rows = trace_rows(prm);
+      hipMemcpyAsync(pr->trace, c.trace, sizeof(double) * 8 * rows, hipMemcpyDeviceToDevice, s);
+    }
+  }
+  int rc = hip_status();
+  if (rc) return rc;
+  std::vector<State> hs(n);
+  for (int p = 0; p < n; ++p)
+    if (hipMemcpyAsync(&hs[p], cs[p].st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return LDDMM_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return LDDMM_EHIP;
+  int worst = LDDMM_OK;
+  for (int p = 0; p < n; ++p) {
+    const Config& k = cs[p].cfg;
+    int st = LDDMM_OK;
+    if (hs[p].nonfinite) {
+      const long long N3 = 3LL * k.lv[k.L - 1].N[0] * k.lv[k.L - 1].N[1] * k.lv[k.L - 1].N[2];
+      if (probs[p].phi10) launch_fill(probs[p].phi10, N3, NAN, s);
+      if (probs[p].phi01) launch_fill(probs[p].phi01, N3, NAN, s);
+      st = LDDMM_ENONFINITE;
+    } else if (hs[p].stopped_any) {
+      st = LDDMM_WGUARD;
+    } else if (hs[p].min_det_all <= 0.0) {
+      st = LDDMM_WFOLD;
+    }
+    if (status) status[p] = st;
+    if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+    if (worst >= 0 && st > worst) worst = st;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return LDDMM_EHIP;
+  return worst;
+}
+
+extern "C" {
 
 int lddmm_energy(const lddmm_problem* p, const lddmm_params* prm, double* out4, void* stream) {
   if (!out4) return LDDMM_EINVAL;

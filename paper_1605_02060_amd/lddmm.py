@@ -80,6 +80,8 @@ def load():
     lib.lddmm_trace_rows.restype = i32
     lib.lddmm_register.argtypes = [P(_Problem), i32, P(_Params), vp]
     lib.lddmm_register.restype = ctypes.c_int
+    lib.lddmm_register_batched.argtypes = [P(_Problem), i32, P(_Params), P(i32), vp]
+    lib.lddmm_register_batched.restype = ctypes.c_int
     lib.lddmm_energy.argtypes = [P(_Problem), P(_Params), vp, vp]
     lib.lddmm_energy.restype = ctypes.c_int
     lib.lddmm_gradient.argtypes = [P(_Problem), P(_Params), i32, vp, vp, vp]
@@ -105,6 +107,7 @@ def load():
 
 
 EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddmm_register",
+            "lddmm_register_batched",
             "lddmm_energy", "lddmm_gradient", "lddmm_apply", "lddmm_smooth_workspace_size",
             "lddmm_smooth", "lddmm_make_mask", "lddmm_profile_begin", "lddmm_profile_end",
             "lddmm_set_tunable", "lddmm_strerror"]
@@ -239,6 +242,40 @@ def lddmm_register(M0, M1, MI0=None, MI1=None, params: Params = None, spacing=1.
     code = load().lddmm_register(ctypes.byref(pr), 1, ctypes.byref(params.c()), _stream(stream))
     _check(code, "lddmm_register", ok=(OK, WFOLD, WGUARD, ENONFINITE))
     return {"v": v, "phi10": phi10, "phi01": phi01, "trace": trace, "status": code}
+
+
+def lddmm_register_batched(pairs, params: Params = None, vs=None, wss=None, want_phi=True,
+                           stream=None):
+    """Register several independent problems of uneven size in one batched launch
+    sequence.  pairs: list of dicts with M0, M1 (and optionally MI0, MI1, spacing).
+    Returns one result dict per problem (as lddmm_register) and the batch status."""
+    params = params or Params()
+    n = len(pairs)
+    arr = (_Problem * n)()
+    keep = []
+    results = []
+    for k, pr in enumerate(pairs):
+        M0, M1 = pr["M0"], pr["M1"]
+        MI0, MI1 = pr.get("MI0"), pr.get("MI1")
+        h = pr.get("spacing", 1.0)
+        dev = M0.device
+        P = lddmm_comp_grid(M0.shape, params, 0, h)
+        v = vs[k] if vs is not None else torch.zeros((params.T, 3) + P, dtype=torch.float32,
+                                                     device=dev)
+        ws = wss[k] if wss is not None else workspace(M0.shape, params, h, dev)
+        rows = lddmm_trace_rows(params)
+        trace = torch.full((rows, TRACE_COLS), float("nan"), dtype=torch.float64, device=dev)
+        phi10 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
+        phi01 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
+        arr[k] = _problem(M0, M1, MI0, MI1, v, h, ws, phi10, phi01, trace)
+        keep.append((M0, M1, MI0, MI1, ws))
+        results.append({"v": v, "phi10": phi10, "phi01": phi01, "trace": trace})
+    status = (ctypes.c_int32 * n)()
+    code = load().lddmm_register_batched(arr, n, ctypes.byref(params.c()), status, _stream(stream))
+    _check(code, "lddmm_register_batched", ok=(OK, WFOLD, WGUARD, ENONFINITE))
+    for k in range(n):
+        results[k]["status"] = int(status[k])
+    return results, code
 
 
 def lddmm_energy(M0, M1, MI0, MI1, v, params: Params, spacing=1.0, ws=None, stream=None):
