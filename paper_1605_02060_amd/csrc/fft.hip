@@ -412,9 +412,22 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd_batched(BatchRef br) {
   x_fwd_body<EMAX>(((const PairTab*)br.tab[p])->fft, blockIdx.x - br.off[p]);
 }
 
+// Launch-shape tunables of the FFT passes (results do not depend on them: every
+// line is transformed the same way whatever the tile it shares a block with).
+static int g_x_elems = kFFTElems;     // complex values per x-pass block
+static int g_col_cap = 16;            // kx columns per y / z tile
+
+void set_fft_x_elems(int e) { g_x_elems = e < 256 ? 256 : (e > 8192 ? 8192 : e); }
+
+void set_fft_cols(int c) {
+  int t = 2;
+  while (t * 2 <= c && t < 32) t *= 2;
+  g_col_cap = t;
+}
+
 // Row pairs per block of the x passes and the register budget they need.
 static int pairs_per_block(int N, int* emax) {
-  int ppb = kFFTElems / (3 * N);
+  int ppb = g_x_elems / (3 * N);
   if (ppb < 1) ppb = 1;
   if (ppb > 8) ppb = 8;
   const int tot = 3 * ppb * N;
@@ -434,7 +447,7 @@ static int ilog2(int v) {
 }
 
 static int tile_cols(int N, int* emax) {
-  int tx = 16;
+  int tx = g_col_cap;
   while (tx > 2 && tx * N > 2 * kFFTElems) tx >>= 1;
   const int tot = tx * N;
   *emax = tot <= kBlock * 8 ? 8 : (tot <= kBlock * 16 ? 16 : 32);

@@ -1144,6 +1144,16 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
     set_sweep_blocks(value);
     return LDDMM_OK;
   }
+  if (which == LDDMM_TUNE_FFT_X_ELEMS) {
+    if (value < 1) return LDDMM_EINVAL;
+    set_fft_x_elems(value);
+    return LDDMM_OK;
+  }
+  if (which == LDDMM_TUNE_FFT_COLS) {
+    if (value < 1) return LDDMM_EINVAL;
+    set_fft_cols(value);
+    return LDDMM_OK;
+  }
   return LDDMM_EINVAL;
 }
 

@@ -246,6 +246,16 @@ def batched_dims(seed=4, n=16, lo=64, hi=160):
     return rng.integers(lo, hi + 1, size=(n, 3))
 
 
+def batched_pair(k, dims=None):
+    """Pair k of the batched workload: the 32^3 blob recipe scaled by
+    s = min(dims)/32 (blob widths 2s-5s, max displacement 3s), seed 400 + k.
+    Returned arrays are [nz][ny][nx]."""
+    dims = batched_dims() if dims is None else dims
+    nx, ny, nz = (int(d) for d in dims[k])
+    s = min(nx, ny, nz) / 32.0
+    return blob_pair((nz, ny, nx), 400 + k, max_disp=3.0 * s, sigma=(2.0 * s, 5.0 * s))
+
+
 def config_pair(name, seed=None):
     """Named synthetic workloads.
 

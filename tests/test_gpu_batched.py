@@ -99,3 +99,52 @@ def test_batched_sixteen_uneven_pairs_timing():
     ts = time.perf_counter() - t0
     print(f"16 pairs x 10 iterations: batched {tb:.3f} s, sequential {ts:.3f} s")
     assert code in (L.OK, L.WFOLD)
+
+
+def test_tunables_do_not_change_results():
+    from paper_1605_02060_amd import tune
+    say("tunables: results independent of launch shapes")
+    p = synth.blob_pair((22, 30, 26), 420, max_disp=2.5, sigma=(1.5, 4.0))
+    M0, M1, MI0, MI1 = t(p.M0), t(p.M1), t(p.MI0), t(p.MI1)
+    prm = L.Params(T=4, iters=(3,), step=0.02, guard=False, weight=(1.0, 0.5))
+    tune.set_all(tune.DEFAULTS)
+    ref = L.lddmm_register(M0, M1, MI0, MI1, params=prm, spacing=0.05)
+    try:
+        for which, values in tune.CANDIDATES.items():
+            for v in values:
+                say(f"tunable {tune.NAMES[which]} = {v}")
+                tune.set_all(tune.DEFAULTS)
+                L.lddmm_set_tunable(which, v)
+                r = L.lddmm_register(M0, M1, MI0, MI1, params=prm, spacing=0.05)
+                torch.cuda.synchronize()
+                assert torch.equal(r["v"], ref["v"]), (which, v)
+                assert torch.equal(r["phi10"], ref["phi10"]) and torch.equal(r["phi01"], ref["phi01"])
+                e, e0 = r["trace"][:, :3], ref["trace"][:, :3]
+                assert torch.allclose(e, e0, rtol=1e-12, atol=0.0), (which, v)
+    finally:
+        tune.set_all(tune.DEFAULTS)
+
+
+def test_autotune_picks_candidates_and_caches(tmp_path, monkeypatch):
+    from paper_1605_02060_amd import tune
+    say("autotune on three uneven pairs")
+    monkeypatch.setenv("LDDMM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    pairs = [d for _, d in _pairs([(24, 20, 28), (30, 26, 18), (20, 32, 24)], seed0=430,
+                                  with_img=False)]
+    prm = L.Params(T=4, iters=(3,), step=0.02, guard=False)
+    try:
+        choice = tune.autotune(pairs, prm, iters=2, repeats=1)
+        for which, v in choice.items():
+            assert v in tune.CANDIDATES[which]
+        assert (tmp_path / "tune.json").exists()
+        again = tune.autotune(pairs, prm)                 # served from the cache
+        assert again == choice
+        res, code = L.lddmm_register_batched(pairs, prm)
+        torch.cuda.synchronize()
+        tune.set_all(tune.DEFAULTS)
+        ref, code0 = L.lddmm_register_batched(pairs, prm)
+        torch.cuda.synchronize()
+        for a, b in zip(res, ref):
+            assert torch.equal(a["v"], b["v"])
+    finally:
+        tune.set_all(tune.DEFAULTS)
