@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm.so")
 
-SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip"]
+SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip", "cnn.hip"]
 ARCH = "gfx950"
 
 

@@ -8,6 +8,7 @@
 
 #include "internal.h"
 #include "lddmm.h"
+#include "lddmm_cnn.h"
 
 namespace lddmm {
 
@@ -1203,3 +1204,41 @@ const char* lddmm_strerror(int code) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- warm-start expansion ----
+
+namespace lddmm {
+
+// planar[ch][vox] = scale * out[vox][ch]
+__global__ void k_unpack_channels(const float* out, long long nvox, int C, float scale,
+                                  float* planar) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * C) return;
+  const long long ch = i / nvox;
+  const long long p = i - ch * nvox;
+  planar[i] = scale * out[p * C + ch];
+}
+
+}  // namespace lddmm
+
+extern "C" int lddmm_cnn_expand_velocity(const float* out, int32_t T, int32_t d, int32_t h,
+                                         int32_t w, float scale, float* v, float* scratch,
+                                         void* stream) {
+  if (!out || !v || !scratch || T < 1 || T > LDDMM_MAX_T || d < 2 || h < 2 || w < 2 ||
+      4 * std::max(d, std::max(h, w)) > LDDMM_MAX_DIM)
+    return LDDMM_EINVAL;
+  const long long nc = (long long)d * h * w;
+  if (3LL * T * 64 * nc >= (1LL << 31)) return LDDMM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const Geom g0 = make_geom(w, h, d, 1.0), g1 = make_geom(2 * w, 2 * h, 2 * d, 1.0),
+             g2 = make_geom(4 * w, 4 * h, 4 * d, 1.0);
+  float* mid = scratch;                          // 3T fields on the 2x grid
+  float* planar = scratch + 3LL * T * g1.n;      // 3T fields on the coarse grid
+  hipGetLastError();
+  const long long total = nc * 3 * T;
+  hipLaunchKernelGGL(k_unpack_channels, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     out, nc, 3 * T, scale, planar);
+  launch_up2(planar, g0, mid, g1, 3 * T, s);
+  launch_up2(mid, g1, v, g2, 3 * T, s);
+  return hip_status();
+}

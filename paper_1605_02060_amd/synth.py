@@ -89,6 +89,24 @@ def eval_blobs(p, x, y, z):
     return out
 
 
+def plane_wave_params(rng, shape, n_waves=6, wavelength=None):
+    """Draw the waves of plane_wave_displacement: list of (k [3] in cycles per voxel
+    (x, y, z), phase, amplitude [3])."""
+    nz, ny, nx = shape
+    ext = float(max(nx, ny, nz))
+    lo, hi = wavelength if wavelength is not None else (1.5 * ext, 3.0 * ext)
+    waves = []
+    for _ in range(n_waves):
+        lam = rng.uniform(lo, hi)
+        dirv = rng.normal(size=3)
+        dirv /= np.linalg.norm(dirv)
+        k = dirv / lam
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        A = rng.normal(size=3)
+        waves.append((k, ph, A))
+    return waves
+
+
 def plane_wave_displacement(rng, shape, max_disp, n_waves=6, wavelength=None):
     """Random smooth displacement d(x) = sum_m A_m sin(2 pi k_m . x + p_m).
 
@@ -97,30 +115,18 @@ def plane_wave_displacement(rng, shape, max_disp, n_waves=6, wavelength=None):
     max_x |d(x)| == max_disp.  The returned bound on |grad d| (Frobenius) is
     analytic: sum over waves of |A_m| * 2 pi |k_m|.
     """
-    nz, ny, nx = shape
-    ext = float(max(nx, ny, nz))
-    lo, hi = wavelength if wavelength is not None else (1.5 * ext, 3.0 * ext)
+    waves = plane_wave_params(rng, shape, n_waves, wavelength)
     x, y, z = _coords(shape)
     d = np.zeros((3,) + tuple(shape), dtype=np.float64)
-    amps = np.zeros((3, n_waves))
-    kn = np.zeros(n_waves)
-    for m in range(n_waves):
-        lam = rng.uniform(lo, hi)
-        dirv = rng.normal(size=3)
-        dirv /= np.linalg.norm(dirv)
-        k = dirv / lam
-        kn[m] = np.linalg.norm(k)
-        ph = rng.uniform(0.0, 2.0 * math.pi)
-        A = rng.normal(size=3)
-        amps[:, m] = A
+    for k, ph, A in waves:
         wave = np.sin(2.0 * math.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
         for comp in range(3):
             d[comp] += A[comp] * wave
     mag = np.sqrt((d * d).sum(axis=0)).max()
     scale = max_disp / mag if mag > 0 else 0.0
     d *= scale
-    amps *= scale
-    lip = float(np.sum(np.linalg.norm(amps, axis=0) * 2.0 * math.pi * kn))
+    lip = float(sum(np.linalg.norm(A) * scale * 2.0 * math.pi * np.linalg.norm(k)
+                    for k, ph, A in waves))
     return d, lip
 
 
@@ -154,6 +160,47 @@ def blob_pair(shape, seed, max_disp=3.0, tau=0.1, n_blobs=8, sigma=(2.0, 5.0),
     M0 = (I0 > tau)
     M1 = (I1 > tau)
     return _finish(I0, I1, M0, M1, d, {"seed": seed, "lipschitz": lip, "kind": "blobs"})
+
+
+def blob_masks_device(shape, seed, device, max_disp=3.0, tau=0.1, n_blobs=8, sigma=(2.0, 5.0),
+                      amp=(0.3, 1.0), center_frac=(10.0 / 32.0, 22.0 / 32.0)):
+    """The masks (M0, M1) of blob_pair(shape, seed, ...), evaluated with torch in
+    float64 on `device` (same draws, same formulas); float32 [nz, ny, nx]."""
+    import torch
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    ext = (nx, ny, nz)
+    lo = tuple(center_frac[0] * e for e in ext)
+    hi = tuple(center_frac[1] * e for e in ext)
+    p = blob_params(rng, n_blobs, sigma, amp, lo, hi)
+    waves = plane_wave_params(rng, shape, 6, None)
+    f64 = torch.float64
+    z, y, x = torch.meshgrid(torch.arange(nz, dtype=f64, device=device),
+                             torch.arange(ny, dtype=f64, device=device),
+                             torch.arange(nx, dtype=f64, device=device), indexing="ij")
+
+    def blobs(x, y, z):
+        out = torch.zeros(x.shape, dtype=f64, device=device)
+        for a, s, c in zip(p["a"], p["s"], p["c"]):
+            r2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2
+            out += a * torch.exp(-r2 / (2.0 * s * s))
+        return out
+
+    d = torch.zeros((3,) + tuple(shape), dtype=f64, device=device)
+    for k, ph, A in waves:
+        wave = torch.sin(2.0 * math.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+        for comp in range(3):
+            d[comp] += A[comp] * wave
+    mag = float(torch.sqrt((d * d).sum(dim=0)).max())
+    d *= max_disp / mag if mag > 0 else 0.0
+    M0 = (blobs(x, y, z) > tau).to(torch.float32)
+    M1 = (blobs(x + d[0], y + d[1], z + d[2]) > tau).to(torch.float32)
+    return M0.contiguous(), M1.contiguous()
+
+
+def warmstart_masks_device(seed, device):
+    """Masks of the warm-start workload pair `seed` (the 96^3 blob recipe x3)."""
+    return blob_masks_device((96, 96, 96), seed, device, max_disp=9.0, sigma=(6.0, 15.0))
 
 
 def _finish(I0, I1, M0, M1, d, meta):

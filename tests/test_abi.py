@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every symbol include/lddmm.h declares
+"""The C-ABI library loads and exports every symbol include/*.h declares
 (CPU only: no compute calls without a GPU)."""
 
 import ctypes
@@ -7,15 +7,23 @@ import re
 
 import pytest
 
+from paper_1605_02060_amd import cnn
 from paper_1605_02060_amd import lddmm as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "lddmm.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lddmm_[a-z_0-9]+)\s*\(", src)))
+def _declared(headers=("lddmm.h", "lddmm_cnn.h")):
+    names = set()
+    for h in headers:
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(lddmm_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_every_header_is_checked():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["lddmm.h", "lddmm_cnn.h"]
 
 
 def test_header_declares_the_boundary_calls():
@@ -28,7 +36,8 @@ def test_library_exports_every_declared_symbol():
     lib = L.load()
     for n in _declared():
         assert hasattr(lib, n), n
-    assert sorted(L.EXPORTED) == _declared()
+    assert sorted(L.EXPORTED + cnn.EXPORTED) == _declared()
+    cnn._lib()                                    # every signature binds
 
 
 def test_struct_layout_matches_header(tmp_path):
