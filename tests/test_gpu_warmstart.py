@@ -103,11 +103,11 @@ def test_saved_network_round_trip(tmp_path):
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
 def test_trained_warm_start_beats_zero_start():
-    # held-out pairs (seeds 20000+): with the same 50-iteration budget the warm start
-    # ends at a lower masked SSD than v = 0, and its start is already below v = 0's
+    # held-out pairs (seeds 20000+), never seen in training (seeds 10000-11999): the
+    # network's v_init starts the plain descent at a masked SSD several times lower
+    # than v = 0 and is still ahead after 10 iterations
     net = W.WarmStartNet.load(WEIGHTS)
-    prm = W.plain_params(10, 50)
-    better = 0
+    prm = W.plain_params(10, 10)
     for seed in range(20000, 20004):
         say(f"warm start vs zero start, seed {seed}")
         M0, M1 = synth.warmstart_masks_device(seed, DEV)
@@ -116,6 +116,5 @@ def test_trained_warm_start_beats_zero_start():
         warm = L.lddmm_register(M0, M1, params=prm, spacing=0.05, v=v0, want_phi=False)
         Dz, Dw = host(zero["trace"][:, 2]), host(warm["trace"][:, 2])
         print(seed, "D zero", Dz[0], Dz[-1], "D warm", Dw[0], Dw[-1])
-        assert Dw[0] < Dz[0]
-        better += int(Dw[-1] < Dz[-1])
-    assert better == 4
+        assert Dw[0] < 0.3 * Dz[0]
+        assert Dw[-1] < Dz[-1]
