@@ -325,6 +325,18 @@ __device__ __forceinline__ bool gate(const State* st, int need_mode) {
 // Every thread moves at most EMAX elements between HBM and LDS; all of its global
 // loads are issued before any LDS write so their latencies overlap.
 
+// Every block first copies the N twiddles of its axis into LDS, after its tile
+// (rounded up to 16 elements): each stage reads up to R - 1 twiddles per
+// butterfly, and from LDS these no longer put an L2 round trip into every stage.
+__device__ __forceinline__ int tw_offset(int tile_elems) { return (tile_elems + 15) & ~15; }
+
+__device__ __forceinline__ const float2* stage_twiddles(float2* sm, int tile_elems,
+                                                        const float2* __restrict__ tw, int N) {
+  float2* t = sm + tw_offset(tile_elems);
+  for (int e = threadIdx.x; e < N; e += kBlock) t[e] = tw[e];
+  return t;
+}
+
 // ----------------------------------------------------------- x forward ----
 // Row rho = z*ny + y.  Rows are processed in pairs (2m, 2m+1): complex lines
 //   Z0 = bx[2m] + i by[2m],  Z1 = bx[2m+1] + i by[2m+1],  Z2 = bz[2m] + i bz[2m+1].
@@ -338,7 +350,6 @@ __device__ __forceinline__ void x_fwd_body(const FftPair& f, int block) {
   float2* __restrict__ S = f.S;
   const Geom& g = f.g;
   const FFTPlan& p = f.px;
-  const float2* __restrict__ tw = f.tw[0];
   const int ppb = f.ppb;
   const int N = g.nx;
   const long long n = g.n;
@@ -346,6 +357,7 @@ __device__ __forceinline__ void x_fwd_body(const FftPair& f, int block) {
   const int pair0 = block * ppb;
   const int nl = 3 * ppb;
   const int tot = nl * N;
+  const float2* tw = stage_twiddles(sm, tot, f.tw[0], N);
   float2 tmp[EMAX];
 #pragma unroll
   for (int r = 0; r < EMAX; ++r) {
@@ -504,8 +516,9 @@ __device__ __forceinline__ void y_body(const FftPair& f, int bx, int bz_slab, in
   const int TX = 1 << lgTX;
   const int kx0 = bx * TX;
   float2* base = f.S + (long long)comp * g.nspec + (long long)bz_slab * g.ny * hs;
+  const float2* tw = stage_twiddles(sm, TX * ls, f.tw[1], N);
   tile_load<EMAX, INV>(sm, base, lgTX, N, ls, hx, kx0, hs);
-  lds_fft<EMAX>(sm, ls, TX, f.py, f.tw[1]);
+  lds_fft<EMAX>(sm, ls, TX, f.py, tw);
   tile_store<INV>(sm, base, lgTX, N, ls, hx, kx0, hs);
 }
 
@@ -534,8 +547,9 @@ __device__ __forceinline__ void zK_body(const FftPair& f, int bx, int ky, int co
   const int kx0 = bx * TX;
   const int zs = g.ny * g.hs;
   float2* base = f.S + (long long)comp * g.nspec + (long long)ky * g.hs;
+  const float2* tw = stage_twiddles(sm, TX * ls, f.tw[2], N);
   tile_load<EMAX, false>(sm, base, lgTX, N, ls, hx, kx0, zs);
-  lds_fft<EMAX>(sm, ls, TX, f.pz, f.tw[2]);
+  lds_fft<EMAX>(sm, ls, TX, f.pz, tw);
   const double inv_n = 1.0 / ((double)g.nx * (double)g.ny * (double)g.nz);
   const double* __restrict__ lamx = f.lam[0];
   const double* __restrict__ lamz = f.lam[2];
@@ -549,7 +563,7 @@ __device__ __forceinline__ void zK_body(const FftPair& f, int bx, int ky, int co
     sm[c * ls + kz] = make_float2(v.x * kh, -v.y * kh);     // conj(K_hat X / |P|)
   }
   __syncthreads();
-  lds_fft<EMAX>(sm, ls, TX, f.pz, f.tw[2]);
+  lds_fft<EMAX>(sm, ls, TX, f.pz, tw);
   tile_store<true>(sm, base, lgTX, N, ls, hx, kx0, zs);
 }
 
@@ -580,7 +594,6 @@ __device__ __forceinline__ void x_inv_body(const FftPair& f, const UpdArgs& u, i
   const float2* __restrict__ S = f.S;
   const Geom& g = f.g;
   const FFTPlan& p = f.px;
-  const float2* __restrict__ tw = f.tw[0];
   const int ppb = f.ppb;
   const int N = g.nx, hx = g.hx, hs = g.hs;
   const long long n = g.n;
@@ -588,6 +601,7 @@ __device__ __forceinline__ void x_inv_body(const FftPair& f, const UpdArgs& u, i
   const int pair0 = block * ppb;
   const int nl = 3 * ppb;
   const int tot = nl * N;
+  const float2* tw = stage_twiddles(sm, tot, f.tw[0], N);
   float2 tA[EMAX], tB[EMAX];
 #pragma unroll
   for (int r = 0; r < EMAX; ++r) {
@@ -696,9 +710,11 @@ void fft_tiles(FftPair& f, FftLaunch* L) {
   L->ex = ex;
   L->ey = ey;
   L->ez = ez;
-  L->x_lds = (size_t)3 * f.ppb * f.g.nx * sizeof(float2);
-  L->y_lds = (size_t)ty * (f.g.ny + 1) * sizeof(float2);
-  L->z_lds = (size_t)tz * (f.g.nz + 1) * sizeof(float2);
+  // tile, rounded up to 16 elements, then the axis twiddles (see stage_twiddles)
+  auto lds = [](size_t tile, int n) { return ((tile + 15) / 16 * 16 + (size_t)n) * sizeof(float2); };
+  L->x_lds = lds((size_t)3 * f.ppb * f.g.nx, f.g.nx);
+  L->y_lds = lds((size_t)ty * (f.g.ny + 1), f.g.ny);
+  L->z_lds = lds((size_t)tz * (f.g.nz + 1), f.g.nz);
 }
 
 #define EMAX_SWITCH(E, CALL8, CALL16, CALL32) \
