@@ -213,9 +213,9 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * backward sweep kernels (rounded to a multiple of 8, clamped to [8, 4096];
  * default 1024).  LDDMM_TUNE_FFT_X_ELEMS: complex values one block of the x
  * passes of K holds in LDS (row pairs per block = value / (3 nx), 1..8; clamped
- * to [256, 8192]; default 2048).  LDDMM_TUNE_FFT_COLS: kx columns per tile of
- * the y and z passes (rounded down to a power of two in [2, 32], then halved
- * while columns x length exceeds 4096; default 16).  Sweep-block counts change
+ * to [256, 8192]; default 2048).  LDDMM_TUNE_FFT_COLS / LDDMM_TUNE_FFT_ZCOLS:
+ * kx columns per tile of the y / the z pass (rounded down to a power of two in
+ * [2, 32], then halved while columns x length exceeds 4096; defaults 16 and 8).  Sweep-block counts change
  * only the order of the FP64 energy partial sums.  A value applies to calls
  * enqueued after it is set.  Returns LDDMM_OK or LDDMM_EINVAL (unknown `which`
  * or value < 1).
@@ -223,6 +223,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 #define LDDMM_TUNE_SWEEP_BLOCKS 0
 #define LDDMM_TUNE_FFT_X_ELEMS  1
 #define LDDMM_TUNE_FFT_COLS     2
+#define LDDMM_TUNE_FFT_ZCOLS    3
 int lddmm_set_tunable(int32_t which, int32_t value);
 
 /* Human-readable text of a status code (static storage). */

@@ -427,15 +427,16 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd_batched(BatchRef br) {
 // Launch-shape tunables of the FFT passes (results do not depend on them: every
 // line is transformed the same way whatever the tile it shares a block with).
 static int g_x_elems = kFFTElems;     // complex values per x-pass block
-static int g_col_cap = 16;            // kx columns per y / z tile
+static int g_col_cap[2] = {16, 8};    // kx columns per y tile, per z tile
 
 void set_fft_x_elems(int e) { g_x_elems = e < 256 ? 256 : (e > 8192 ? 8192 : e); }
 
-void set_fft_cols(int c) {
+static int pow2_cap(int c) {
   int t = 2;
   while (t * 2 <= c && t < 32) t *= 2;
-  g_col_cap = t;
+  return t;
 }
+void set_fft_cols(int axis, int c) { g_col_cap[axis] = pow2_cap(c); }
 
 // Row pairs per block of the x passes and the register budget they need.
 static int pairs_per_block(int N, int* emax) {
@@ -458,8 +459,8 @@ static int ilog2(int v) {
   return k;
 }
 
-static int tile_cols(int N, int* emax) {
-  int tx = g_col_cap;
+static int tile_cols(int N, int axis, int* emax) {
+  int tx = g_col_cap[axis];
   while (tx > 2 && tx * N > 2 * kFFTElems) tx >>= 1;
   const int tot = tx * N;
   *emax = tot <= kBlock * 8 ? 8 : (tot <= kBlock * 16 ? 16 : 32);
@@ -602,29 +603,30 @@ __device__ __forceinline__ void x_inv_body(const FftPair& f, const UpdArgs& u, i
   const int nl = 3 * ppb;
   const int tot = nl * N;
   const float2* tw = stage_twiddles(sm, tot, f.tw[0], N);
+  // each half-spectrum value is read once and written to k and to its mirror N - k
+  const int toth = nl * hx;
   float2 tA[EMAX], tB[EMAX];
 #pragma unroll
   for (int r = 0; r < EMAX; ++r) {
     const int e = threadIdx.x + r * kBlock;
     float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-    if (e < tot) {
-      const int l = (int)fdiv((uint32_t)e, g.fx), k = e - l * N;
+    if (e < toth) {
+      const int l = (int)fdiv((uint32_t)e, g.fhx), k = e - l * hx;
       const int pp = l / 3, which = l - 3 * pp;
       const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
-      const int kk = k < hx ? k : N - k;
       if (which == 0) {
         if (r0 < nrows) {
-          A = S[(long long)r0 * hs + kk];
-          B = S[g.nspec + (long long)r0 * hs + kk];
+          A = S[(long long)r0 * hs + k];
+          B = S[g.nspec + (long long)r0 * hs + k];
         }
       } else if (which == 1) {
         if (r1 < nrows) {
-          A = S[(long long)r1 * hs + kk];
-          B = S[g.nspec + (long long)r1 * hs + kk];
+          A = S[(long long)r1 * hs + k];
+          B = S[g.nspec + (long long)r1 * hs + k];
         }
       } else {
-        if (r0 < nrows) A = S[2 * g.nspec + (long long)r0 * hs + kk];
-        if (r1 < nrows) B = S[2 * g.nspec + (long long)r1 * hs + kk];
+        if (r0 < nrows) A = S[2 * g.nspec + (long long)r0 * hs + k];
+        if (r1 < nrows) B = S[2 * g.nspec + (long long)r1 * hs + k];
       }
     }
     tA[r] = A;
@@ -633,15 +635,13 @@ __device__ __forceinline__ void x_inv_body(const FftPair& f, const UpdArgs& u, i
 #pragma unroll
   for (int r = 0; r < EMAX; ++r) {
     const int e = threadIdx.x + r * kBlock;
-    if (e < tot) {
-      const int k = e - (int)fdiv((uint32_t)e, g.fx) * N;
-      float2 A = tA[r], B = tB[r];
-      if (k >= hx) {
-        A = cconj(A);
-        B = cconj(B);
-      }
-      // Z = A + i B ; store conj(Z) for the forward transform of the inverse
-      sm[e] = make_float2(A.x - B.y, -(A.y + B.x));
+    if (e < toth) {
+      const int l = (int)fdiv((uint32_t)e, g.fhx), k = e - l * hx;
+      const float2 A = tA[r], B = tB[r];
+      // Z = A + i B, stored as conj(Z) for the forward transform of the inverse;
+      // the upper half holds Z[N - k] = conj A[k] + i conj B[k]
+      sm[l * N + k] = make_float2(A.x - B.y, -(A.y + B.x));
+      if (k >= 1 && N - k >= hx) sm[l * N + N - k] = make_float2(A.x + B.y, A.y - B.x);
     }
   }
   __syncthreads();
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv_batched(BatchRef br, int j
 void fft_tiles(FftPair& f, FftLaunch* L) {
   int ex, ey, ez;
   f.ppb = pairs_per_block(f.g.nx, &ex);
-  const int ty = tile_cols(f.g.ny, &ey), tz = tile_cols(f.g.nz, &ez);
+  const int ty = tile_cols(f.g.ny, 0, &ey), tz = tile_cols(f.g.nz, 1, &ez);
   f.lgTXy = ilog2(ty);
   f.lgTXz = ilog2(tz);
   f.nbx_y = (f.g.hx + ty - 1) / ty;

@@ -208,7 +208,7 @@ void launch_up2(const float* src, const Geom& coarse, float* dst, const Geom& fi
 int reduce_grid(long long n);
 void set_sweep_blocks(int blocks);
 void set_fft_x_elems(int elems);
-void set_fft_cols(int cols);
+void set_fft_cols(int axis, int cols);   // axis 0: y tiles, 1: z tiles
 void launch_forward(const FwdArgs& a, hipStream_t s);
 void launch_backward(const BwdArgs& a, hipStream_t s);
 void launch_forward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);

@@ -1150,9 +1150,9 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
     set_fft_x_elems(value);
     return LDDMM_OK;
   }
-  if (which == LDDMM_TUNE_FFT_COLS) {
+  if (which == LDDMM_TUNE_FFT_COLS || which == LDDMM_TUNE_FFT_ZCOLS) {
     if (value < 1) return LDDMM_EINVAL;
-    set_fft_cols(value);
+    set_fft_cols(which == LDDMM_TUNE_FFT_COLS ? 0 : 1, value);
     return LDDMM_OK;
   }
   return LDDMM_EINVAL;

@@ -115,6 +115,7 @@ EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddm
 TUNE_SWEEP_BLOCKS = 0
 TUNE_FFT_X_ELEMS = 1
 TUNE_FFT_COLS = 2
+TUNE_FFT_ZCOLS = 3
 
 PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
                 "other"]
