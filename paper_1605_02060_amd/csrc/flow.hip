@@ -316,6 +316,255 @@ __global__ __launch_bounds__(kBlock) void k_backward_batched(BatchRef br, int sl
                                          br.off[p + 1] - br.off[p]);
 }
 
+// ------------------------------------------- backward sweep, LDS-staged ----
+// The same step as backward_body (a map step u1_j from u1_{j+1} when HAS_U, and
+// the body force b_{j+1}), with the gathers and stencils of u1_{j+1} and the
+// stencil of the deformed template read from LDS.  A block owns a kBX x kBY
+// column of (x, y) and marches up one z-slab.  It keeps a ring of the kBH-halo
+// planes z - kBH .. z + kBH of u1_{j+1} and the planes z - 1 .. z + 1 of the
+// template, loading one new plane of each per step while the step computes.  A
+// map gather whose cell leaves that window (|dt v / h| >= kBH) reads global
+// memory instead.  The arithmetic, and its order, is that of backward_body, so
+// both give the same bits.
+constexpr int kBX = 32, kBY = 8, kBH = 2;
+constexpr int kBRing = 2 * kBH + 1;
+constexpr int kBXH = kBX + 2 * kBH, kBYH = kBY + 2 * kBH;     // map window
+constexpr int kBXJ = kBX + 2, kBYJ = kBY + 2;                 // template window
+constexpr int kUPlane = 3 * kBYH * kBXH;
+constexpr int kURegs = (kUPlane + kBlock - 1) / kBlock;
+static_assert(kBX * kBY == kBlock, "one voxel per thread and plane");
+
+struct BwdTiling {
+  int ntx, nty, nslab;
+};
+
+static BwdTiling bwd_tiling(const Geom& g) {
+  BwdTiling t;
+  t.ntx = (g.nx + kBX - 1) / kBX;
+  t.nty = (g.ny + kBY - 1) / kBY;
+  const int per = g.nz / (kXCD * 15);                 // about 15 planes per slab
+  t.nslab = kXCD * (per < 1 ? 1 : per);
+  return t;
+}
+
+// The staged kernel runs when its blocks fit the partial buffer and every
+// byte offset of a map (3 n floats) fits 32 bits.
+static bool bwd_staged(const Geom& g) {
+  const BwdTiling t = bwd_tiling(g);
+  return (long long)t.ntx * t.nty * t.nslab <= kPartMax && 3LL * g.n < (1LL << 30);
+}
+
+int backward_partials(const Geom& g) {
+  if (!bwd_staged(g)) return reduce_grid(g.n);
+  const BwdTiling t = bwd_tiling(g);
+  return t.ntx * t.nty * t.nslab;
+}
+
+__device__ __forceinline__ float dstencil_v(float plus, float minus, float center, int c, int n,
+                                            float inv_h) {
+  const float vp = (c == n - 1) ? center : plus;
+  const float vm = (c == 0) ? center : minus;
+  const float sc = (c == 0 || c == n - 1) ? inv_h : 0.5f * inv_h;
+  return (vp - vm) * sc;
+}
+
+template <int NC, bool HAS_U>
+__global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a, BwdTiling tl) {
+  __shared__ float su[3][kBRing][kBYH][kBXH];
+  __shared__ float sj[NC][3][kBYJ][kBXJ];
+  constexpr int kJPlane = NC * kBYJ * kBXJ;
+  constexpr int kJRegs = (kJPlane + kBlock - 1) / kBlock;
+  const State* st = a.st;
+  if (a.need_mode >= 0 && st->mode != a.need_mode) return;   // uniform over the grid
+  const Geom g = a.g;
+  const long long N = g.n;
+  const uint32_t n = (uint32_t)N;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const float dt = a.dt, ih = g.inv_h;
+  const float* vb = (a.vfix ? a.vfix : (st->base ? a.vB : a.vA)) +
+                    (long long)(a.j >= 0 ? a.j : 0) * 3 * N;
+  const rsrc_t V0 = rsrc(vb, n), V1 = rsrc(vb + N, n), V2 = rsrc(vb + 2 * N, n);
+  const float* un = a.u_next;
+  const rsrc_t UN = rsrc(un, 3u * n);                   // all three components
+  const rsrc_t N0 = rsrc(un, n), N1 = rsrc(un + N, n), N2 = rsrc(un + 2 * N, n);
+  float* uc = a.u_cur ? a.u_cur : a.b;                  // unused when !HAS_U
+  const rsrc_t C0 = rsrc(uc, n), C1 = rsrc(uc + N, n), C2 = rsrc(uc + 2 * N, n);
+  const rsrc_t B0 = rsrc(a.b, n), B1 = rsrc(a.b + N, n), B2 = rsrc(a.b + 2 * N, n);
+  rsrc_t RR[NC], JJ[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    RR[c] = rsrc(a.r + (long long)c * N, n);
+    JJ[c] = rsrc(a.J0t + (long long)c * a.cstride, n);
+  }
+  // block -> (tile, slab); the slabs of XCD x are x, x + 8, ...
+  const int ntile = tl.ntx * tl.nty;
+  const int xcd = blockIdx.x % kXCD, local = blockIdx.x / kXCD;
+  const int slab = xcd + kXCD * (local / ntile), tile = local % ntile;
+  const int x0 = (tile % tl.ntx) * kBX, y0 = (tile / tl.ntx) * kBY;
+  const int zbeg = (int)((long long)slab * nz / tl.nslab);
+  const int zend = (int)((long long)(slab + 1) * nz / tl.nslab);
+  const int tx = threadIdx.x % kBX, ty = threadIdx.x / kBX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool inside = x < nx && y < ny;
+
+  float ureg[kURegs], jreg[kJRegs];
+  auto fetch_u = [&](int p) {
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      float val = 0.f;
+      if (e < kUPlane && p >= 0 && p < nz) {
+        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
+        const int ly = rem / kBXH, lx = rem - ly * kBXH;
+        const int gx = x0 - kBH + lx, gy = y0 - kBH + ly;
+        if ((unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny)
+          val = bld(UN, (uint32_t)c * n + (uint32_t)((p * ny + gy) * nx + gx));
+      }
+      ureg[r] = val;
+    }
+  };
+  auto put_u = [&](int p) {
+    if (p < 0) return;
+    const int slot = p % kBRing;
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e < kUPlane) {
+        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
+        const int ly = rem / kBXH, lx = rem - ly * kBXH;
+        su[c][slot][ly][lx] = ureg[r];
+      }
+    }
+  };
+  auto fetch_j = [&](int p) {
+#pragma unroll
+    for (int r = 0; r < kJRegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      float val = 0.f;
+      if (e < kJPlane && p >= 0 && p < nz) {
+        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
+        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        if ((unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny) {
+          const uint32_t o = (uint32_t)((p * ny + gy) * nx + gx);
+          val = c == 0 ? bld(JJ[0], o) : bld(JJ[NC - 1], o);
+        }
+      }
+      jreg[r] = val;
+    }
+  };
+  auto put_j = [&](int p) {
+    if (p < 0) return;
+    const int slot = p % 3;
+#pragma unroll
+    for (int r = 0; r < kJRegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e < kJPlane) {
+        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
+        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
+        sj[c][slot][ly][lx] = jreg[r];
+      }
+    }
+  };
+
+  // fill the rings with the planes below the first step's top plane
+  for (int p = zbeg - kBH; p < zbeg + kBH; ++p) {
+    fetch_u(p);
+    put_u(p);
+  }
+  fetch_j(zbeg - 1);
+  put_j(zbeg - 1);
+  fetch_j(zbeg);
+  put_j(zbeg);
+  fetch_u(zbeg + kBH);
+  fetch_j(zbeg + 1);
+
+  const uint32_t sy = (uint32_t)nx, sz = (uint32_t)(nx * ny);
+  const int lx = tx + kBH, ly = ty + kBH;                    // own position in the map window
+  double mind = 1e300;
+  for (int z = zbeg; z < zend; ++z) {
+    put_u(z + kBH);
+    put_j(z + 1);
+    __syncthreads();
+    fetch_u(z + kBH + 1);                                    // in flight during the step
+    fetch_j(z + 2);
+    if (inside) {
+      const uint32_t i = (uint32_t)((z * ny + y) * nx + x);
+      const int s0 = z % kBRing;
+      if (HAS_U) {
+        const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
+        float ux = dt * vx, uy = dt * vy, uz = dt * vz;
+        int cx, cy, cz;
+        float fx, fy, fz;
+        cell_clamp(x, dt * vx * ih, nx, cx, fx);
+        cell_clamp(y, dt * vy * ih, ny, cy, fy);
+        cell_clamp(z, dt * vz * ih, nz, cz, fz);
+        const int wx = cx - (x0 - kBH), wy = cy - (y0 - kBH);
+        if (wx >= 0 && wx + 1 < kBXH && wy >= 0 && wy + 1 < kBYH && cz >= z - kBH &&
+            cz + 1 <= z + kBH) {
+          const int za = cz % kBRing, zb = (cz + 1) % kBRing;
+          float gv[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            gv[c] = lerp8(su[c][za][wy][wx], su[c][za][wy][wx + 1], su[c][za][wy + 1][wx],
+                          su[c][za][wy + 1][wx + 1], su[c][zb][wy][wx], su[c][zb][wy][wx + 1],
+                          su[c][zb][wy + 1][wx], su[c][zb][wy + 1][wx + 1], fx, fy, fz);
+          ux += gv[0];
+          uy += gv[1];
+          uz += gv[2];
+        } else {
+          const Cell cl = make_cell_clamp(g, x, y, z, dt * vx * ih, dt * vy * ih, dt * vz * ih);
+          ux += sample(N0, cl);
+          uy += sample(N1, cl);
+          uz += sample(N2, cl);
+        }
+        bst(C0, i, ux);
+        bst(C1, i, uy);
+        bst(C2, i, uz);
+      }
+      // Jacobian matrix I + D u of u1 at time jb (rows: component, columns: direction)
+      const int sm1 = (z + kBRing - 1) % kBRing, sp1 = (z + 1) % kBRing;
+      float J[3][3], ucen[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float ce = su[c][s0][ly][lx];
+        ucen[c] = ce;
+        J[c][0] = dstencil_v(su[c][s0][ly][lx + 1], su[c][s0][ly][lx - 1], ce, x, nx, ih);
+        J[c][1] = dstencil_v(su[c][s0][ly + 1][lx], su[c][s0][ly - 1][lx], ce, y, ny, ih);
+        J[c][2] = dstencil_v(su[c][sp1][ly][lx], su[c][sm1][ly][lx], ce, z, nz, ih);
+      }
+      J[0][0] += 1.f;
+      J[1][1] += 1.f;
+      J[2][2] += 1.f;
+      const float det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                        J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      mind = fmin(mind, (double)det);
+      const Cell czc = make_cell_zero(g, x, y, z, ucen[0] * ih, ucen[1] * ih, ucen[2] * ih);
+      const int j0 = z % 3, jm = (z + 2) % 3, jp = (z + 1) % 3;
+      const int jx = tx + 1, jy = ty + 1;
+      float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float rw = a.w[c] * sample(RR[c], czc);
+        const float ce = sj[c][j0][jy][jx];
+        bx += rw * dstencil_v(sj[c][j0][jy][jx + 1], sj[c][j0][jy][jx - 1], ce, x, nx, ih);
+        by += rw * dstencil_v(sj[c][j0][jy + 1][jx], sj[c][j0][jy - 1][jx], ce, y, ny, ih);
+        bz += rw * dstencil_v(sj[c][jp][jy][jx], sj[c][jm][jy][jx], ce, z, nz, ih);
+      }
+      const float sc = a.coef * det;
+      bst(B0, i, sc * bx);
+      bst(B1, i, sc * by);
+      bst(B2, i, sc * bz);
+    }
+    __syncthreads();
+  }
+  const double m = block_min(mind);
+  if (threadIdx.x == 0) a.partDet[blockIdx.x] = m;
+  (void)sy;
+  (void)sz;
+}
+
 template <int NC>
 static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
   const int grid = reduce_grid(a.g.n);
@@ -331,6 +580,23 @@ static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
 }
 
 void launch_backward(const BwdArgs& a, hipStream_t s) {
+  const bool hu = a.j >= 0, uz = (a.u_next == nullptr), hb = (a.jb >= 0 && a.jb < a.T);
+  if (hb && !uz && bwd_staged(a.g)) {
+    const BwdTiling t = bwd_tiling(a.g);
+    const dim3 grid(t.ntx * t.nty * t.nslab);
+    if (a.nch == 2) {
+      if (hu)
+        hipLaunchKernelGGL((k_backward_staged<2, true>), grid, dim3(kBlock), 0, s, a, t);
+      else
+        hipLaunchKernelGGL((k_backward_staged<2, false>), grid, dim3(kBlock), 0, s, a, t);
+    } else {
+      if (hu)
+        hipLaunchKernelGGL((k_backward_staged<1, true>), grid, dim3(kBlock), 0, s, a, t);
+      else
+        hipLaunchKernelGGL((k_backward_staged<1, false>), grid, dim3(kBlock), 0, s, a, t);
+    }
+    return;
+  }
   if (a.nch == 2)
     bwd_dispatch<2>(a, s);
   else

@@ -549,9 +549,10 @@ static void exact_gradient(Ctx& c, const float* v, float* grad, hipStream_t s) {
 static void decide(Ctx& c, int li, int init, double* trace, hipStream_t s) {
   const Level& L = c.cfg.lv[li];
   const int nb = reduce_grid(L.g.n);
+  const int nbw = backward_partials(L.g);
   const double h = (double)L.g.h;
   ProfScope ps(LDDMM_PROF_OTHER, 0, s);
-  launch_decide(c.st, c.partR, c.cfg.T, c.partD, c.partI, c.partDet, nb, nb, c.cfg.C > 1,
+  launch_decide(c.st, c.partR, c.cfg.T, c.partD, c.partI, c.partDet, nb, nbw, c.cfg.C > 1,
                 1.0 / c.cfg.T, h * h * h, 1.0 / (c.sigma * c.sigma), c.guard, trace, init, s);
 }
 
