@@ -214,12 +214,7 @@ static void fwd_dispatch(const FwdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_forward<NC, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
 }
 
-void launch_forward(const FwdArgs& a, hipStream_t s) {
-  if (a.nch == 2)
-    fwd_dispatch<2>(a, s);
-  else
-    fwd_dispatch<1>(a, s);
-}
+
 
 // --------------------------------------------------------- backward sweep ----
 
@@ -317,29 +312,32 @@ __global__ __launch_bounds__(kBlock) void k_backward_batched(BatchRef br, int sl
 }
 
 // ------------------------------------------- backward sweep, LDS-staged ----
-// The same step as backward_body (a map step u1_j from u1_{j+1} when HAS_U, and
-// the body force b_{j+1}), with the gathers and stencils of u1_{j+1} and the
-// stencil of the deformed template read from LDS.  A block owns a kBX x kBY
-// column of (x, y) and marches up one z-slab.  It keeps a ring of the kBH-halo
-// planes z - kBH .. z + kBH of u1_{j+1} and the planes z - 1 .. z + 1 of the
-// template, loading one new plane of each per step while the step computes.  A
-// map gather whose cell leaves that window (|dt v / h| >= kBH) reads global
-// memory instead.  The arithmetic, and its order, is that of backward_body, so
-// both give the same bits.
+// The body-force steps of backward_body, with the gathers and stencils of
+// u1_{j+1} and the stencil of the deformed template read from LDS.  A block owns
+// a kBX x kBY column of (x, y) and marches up one z-slab, keeping rings of planes
+// in LDS and loading one new plane of each per step while the step computes:
+//  - u1_{j+1}: planes z - kBH .. z + kBH with an (x, y) halo of kBH, clamped to
+//    the grid.  A map gather whose cell leaves this window (|dt v / h| >= kBH)
+//    reads global memory;
+//  - the deformed template: planes z - 1 .. z + 1, halo 1 (its gradient).
+// The residual gather (displacements of many voxels) stays in global memory.
+// The arithmetic and its order are those of backward_body, so both give the
+// same bits.  (The same staging of the forward step measured no faster: its
+// cost is in the template gather, which cannot be staged.)
 constexpr int kBX = 32, kBY = 8, kBH = 2;
 constexpr int kBRing = 2 * kBH + 1;
 constexpr int kBXH = kBX + 2 * kBH, kBYH = kBY + 2 * kBH;     // map window
-constexpr int kBXJ = kBX + 2, kBYJ = kBY + 2;                 // template window
+constexpr int kBXJ = kBX + 2, kBYJ = kBY + 2;                 // halo-1 window
 constexpr int kUPlane = 3 * kBYH * kBXH;
 constexpr int kURegs = (kUPlane + kBlock - 1) / kBlock;
 static_assert(kBX * kBY == kBlock, "one voxel per thread and plane");
 
-struct BwdTiling {
+struct SweepTiling {
   int ntx, nty, nslab;
 };
 
-static BwdTiling bwd_tiling(const Geom& g) {
-  BwdTiling t;
+__host__ __device__ inline SweepTiling sweep_tiling(const Geom& g) {
+  SweepTiling t;
   t.ntx = (g.nx + kBX - 1) / kBX;
   t.nty = (g.ny + kBY - 1) / kBY;
   const int per = g.nz / (kXCD * 15);                 // about 15 planes per slab
@@ -347,18 +345,132 @@ static BwdTiling bwd_tiling(const Geom& g) {
   return t;
 }
 
-// The staged kernel runs when its blocks fit the partial buffer and every
-// byte offset of a map (3 n floats) fits 32 bits.
-static bool bwd_staged(const Geom& g) {
-  const BwdTiling t = bwd_tiling(g);
+// The staged kernel runs when its blocks fit the partial buffer and every byte
+// offset into a map (3 n floats) fits 32 bits.
+__host__ __device__ inline bool sweep_staged(const Geom& g) {
+  const SweepTiling t = sweep_tiling(g);
   return (long long)t.ntx * t.nty * t.nslab <= kPartMax && 3LL * g.n < (1LL << 30);
 }
 
+// Blocks (and min-det partials) of one body-force launch of this grid.
 int backward_partials(const Geom& g) {
-  if (!bwd_staged(g)) return reduce_grid(g.n);
-  const BwdTiling t = bwd_tiling(g);
+  if (!sweep_staged(g)) return reduce_grid(g.n);
+  const SweepTiling t = sweep_tiling(g);
   return t.ntx * t.nty * t.nslab;
 }
+
+struct SlabTile {
+  int x0, y0, zbeg, zend;
+};
+
+// Block -> (column, slab).  Blocks run on XCD block mod 8; the slabs of XCD x
+// are x, x + 8, ..., so each XCD's L2 serves disjoint z-ranges.
+__device__ __forceinline__ SlabTile slab_tile(const Geom& g, int block) {
+  const SweepTiling tl = sweep_tiling(g);
+  const int ntile = tl.ntx * tl.nty;
+  const int xcd = block % kXCD, local = block / kXCD;
+  const int slab = xcd + kXCD * (local / ntile), tile = local % ntile;
+  SlabTile t;
+  t.x0 = (tile % tl.ntx) * kBX;
+  t.y0 = (tile / tl.ntx) * kBY;
+  t.zbeg = (int)((long long)slab * g.nz / tl.nslab);
+  t.zend = (int)((long long)(slab + 1) * g.nz / tl.nslab);
+  return t;
+}
+
+
+// Ring of map planes (3 components, halo kBH, clamped) staged through registers.
+struct MapRing {
+  float (*s)[kBRing][kBYH][kBXH];
+  float reg[kURegs];
+  __device__ __forceinline__ void fetch(rsrc_t U, uint32_t n, const Geom& g, int x0, int y0, int p) {
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      float val = 0.f;
+      if (e < kUPlane && p >= 0 && p < g.nz) {
+        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
+        const int ly = rem / kBXH, lx = rem - ly * kBXH;
+        const int gx = x0 - kBH + lx, gy = y0 - kBH + ly;
+        if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny)
+          val = bld(U, (uint32_t)c * n + (uint32_t)((p * g.ny + gy) * g.nx + gx));
+      }
+      reg[r] = val;
+    }
+  }
+  __device__ __forceinline__ void put(int p) {
+    if (p < 0) return;
+    const int slot = p % kBRing;
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e < kUPlane) {
+        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
+        const int ly = rem / kBXH, lx = rem - ly * kBXH;
+        s[c][slot][ly][lx] = reg[r];
+      }
+    }
+  }
+  // Trilinear sample of all three components at the clamped cell (cx, cy, cz),
+  // if its 8 corners are in the window of step z.
+  __device__ __forceinline__ bool sample3(int x0, int y0, int z, int cx, int cy, int cz, float fx,
+                                          float fy, float fz, float out[3]) const {
+    const int wx = cx - (x0 - kBH), wy = cy - (y0 - kBH);
+    if (!(wx >= 0 && wx + 1 < kBXH && wy >= 0 && wy + 1 < kBYH && cz >= z - kBH &&
+          cz + 1 <= z + kBH))
+      return false;
+    const int za = cz % kBRing, zb = (cz + 1) % kBRing;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      out[c] = lerp8(s[c][za][wy][wx], s[c][za][wy][wx + 1], s[c][za][wy + 1][wx],
+                     s[c][za][wy + 1][wx + 1], s[c][zb][wy][wx], s[c][zb][wy][wx + 1],
+                     s[c][zb][wy + 1][wx], s[c][zb][wy + 1][wx + 1], fx, fy, fz);
+    return true;
+  }
+};
+
+// Ring of K-component planes z - 1 .. z + 1 with halo 1 (zero outside the grid).
+template <int K>
+struct HaloRing {
+  static constexpr int kPlane = K * kBYJ * kBXJ;
+  static constexpr int kRegs = (kPlane + kBlock - 1) / kBlock;
+  float (*s)[3][kBYJ][kBXJ];
+  float reg[kRegs];
+  // component c of plane p lives at base[c] (element offsets in one descriptor)
+  __device__ __forceinline__ void fetch(const rsrc_t* R, uint32_t n, const Geom& g, int x0,
+                                        int y0, int p) {
+    const int pw = p;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      float val = 0.f;
+      if (e < kPlane && pw >= 0 && pw < g.nz) {
+        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
+        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
+        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+        if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny) {
+          const uint32_t o = (uint32_t)((pw * g.ny + gy) * g.nx + gx);
+          val = bld(R[c < K ? c : K - 1], o);
+        }
+      }
+      reg[r] = val;
+    }
+    (void)n;
+  }
+  __device__ __forceinline__ void put(int p) {
+    if (p < 0) return;
+    const int slot = p % 3;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e < kPlane) {
+        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
+        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
+        s[c][slot][ly][lx] = reg[r];
+      }
+    }
+  }
+};
 
 __device__ __forceinline__ float dstencil_v(float plus, float minus, float center, int c, int n,
                                             float inv_h) {
@@ -369,11 +481,9 @@ __device__ __forceinline__ float dstencil_v(float plus, float minus, float cente
 }
 
 template <int NC, bool HAS_U>
-__global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a, BwdTiling tl) {
+__device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block) {
   __shared__ float su[3][kBRing][kBYH][kBXH];
   __shared__ float sj[NC][3][kBYJ][kBXJ];
-  constexpr int kJPlane = NC * kBYJ * kBXJ;
-  constexpr int kJRegs = (kJPlane + kBlock - 1) / kBlock;
   const State* st = a.st;
   if (a.need_mode >= 0 && st->mode != a.need_mode) return;   // uniform over the grid
   const Geom g = a.g;
@@ -396,98 +506,34 @@ __global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a, BwdTiling
     RR[c] = rsrc(a.r + (long long)c * N, n);
     JJ[c] = rsrc(a.J0t + (long long)c * a.cstride, n);
   }
-  // block -> (tile, slab); the slabs of XCD x are x, x + 8, ...
-  const int ntile = tl.ntx * tl.nty;
-  const int xcd = blockIdx.x % kXCD, local = blockIdx.x / kXCD;
-  const int slab = xcd + kXCD * (local / ntile), tile = local % ntile;
-  const int x0 = (tile % tl.ntx) * kBX, y0 = (tile / tl.ntx) * kBY;
-  const int zbeg = (int)((long long)slab * nz / tl.nslab);
-  const int zend = (int)((long long)(slab + 1) * nz / tl.nslab);
+  const SlabTile tt = slab_tile(g, block);
   const int tx = threadIdx.x % kBX, ty = threadIdx.x / kBX;
-  const int x = x0 + tx, y = y0 + ty;
+  const int x = tt.x0 + tx, y = tt.y0 + ty;
   const bool inside = x < nx && y < ny;
-
-  float ureg[kURegs], jreg[kJRegs];
-  auto fetch_u = [&](int p) {
-#pragma unroll
-    for (int r = 0; r < kURegs; ++r) {
-      const int e = threadIdx.x + r * kBlock;
-      float val = 0.f;
-      if (e < kUPlane && p >= 0 && p < nz) {
-        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
-        const int ly = rem / kBXH, lx = rem - ly * kBXH;
-        const int gx = x0 - kBH + lx, gy = y0 - kBH + ly;
-        if ((unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny)
-          val = bld(UN, (uint32_t)c * n + (uint32_t)((p * ny + gy) * nx + gx));
-      }
-      ureg[r] = val;
-    }
-  };
-  auto put_u = [&](int p) {
-    if (p < 0) return;
-    const int slot = p % kBRing;
-#pragma unroll
-    for (int r = 0; r < kURegs; ++r) {
-      const int e = threadIdx.x + r * kBlock;
-      if (e < kUPlane) {
-        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
-        const int ly = rem / kBXH, lx = rem - ly * kBXH;
-        su[c][slot][ly][lx] = ureg[r];
-      }
-    }
-  };
-  auto fetch_j = [&](int p) {
-#pragma unroll
-    for (int r = 0; r < kJRegs; ++r) {
-      const int e = threadIdx.x + r * kBlock;
-      float val = 0.f;
-      if (e < kJPlane && p >= 0 && p < nz) {
-        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
-        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-        if ((unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny) {
-          const uint32_t o = (uint32_t)((p * ny + gy) * nx + gx);
-          val = c == 0 ? bld(JJ[0], o) : bld(JJ[NC - 1], o);
-        }
-      }
-      jreg[r] = val;
-    }
-  };
-  auto put_j = [&](int p) {
-    if (p < 0) return;
-    const int slot = p % 3;
-#pragma unroll
-    for (int r = 0; r < kJRegs; ++r) {
-      const int e = threadIdx.x + r * kBlock;
-      if (e < kJPlane) {
-        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
-        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
-        sj[c][slot][ly][lx] = jreg[r];
-      }
-    }
-  };
-
-  // fill the rings with the planes below the first step's top plane
-  for (int p = zbeg - kBH; p < zbeg + kBH; ++p) {
-    fetch_u(p);
-    put_u(p);
+  MapRing mu;
+  mu.s = su;
+  HaloRing<NC> rj;
+  rj.s = sj;
+  for (int p = tt.zbeg - kBH; p < tt.zbeg + kBH; ++p) {
+    mu.fetch(UN, n, g, tt.x0, tt.y0, p);
+    mu.put(p);
   }
-  fetch_j(zbeg - 1);
-  put_j(zbeg - 1);
-  fetch_j(zbeg);
-  put_j(zbeg);
-  fetch_u(zbeg + kBH);
-  fetch_j(zbeg + 1);
+  rj.fetch(JJ, n, g, tt.x0, tt.y0, tt.zbeg - 1);
+  rj.put(tt.zbeg - 1);
+  rj.fetch(JJ, n, g, tt.x0, tt.y0, tt.zbeg);
+  rj.put(tt.zbeg);
+  mu.fetch(UN, n, g, tt.x0, tt.y0, tt.zbeg + kBH);
+  rj.fetch(JJ, n, g, tt.x0, tt.y0, tt.zbeg + 1);
 
-  const uint32_t sy = (uint32_t)nx, sz = (uint32_t)(nx * ny);
   const int lx = tx + kBH, ly = ty + kBH;                    // own position in the map window
+  const int jx = tx + 1, jy = ty + 1;
   double mind = 1e300;
-  for (int z = zbeg; z < zend; ++z) {
-    put_u(z + kBH);
-    put_j(z + 1);
+  for (int z = tt.zbeg; z < tt.zend; ++z) {
+    mu.put(z + kBH);
+    rj.put(z + 1);
     __syncthreads();
-    fetch_u(z + kBH + 1);                                    // in flight during the step
-    fetch_j(z + 2);
+    mu.fetch(UN, n, g, tt.x0, tt.y0, z + kBH + 1);           // in flight during the step
+    rj.fetch(JJ, n, g, tt.x0, tt.y0, z + 2);
     if (inside) {
       const uint32_t i = (uint32_t)((z * ny + y) * nx + x);
       const int s0 = z % kBRing;
@@ -499,25 +545,16 @@ __global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a, BwdTiling
         cell_clamp(x, dt * vx * ih, nx, cx, fx);
         cell_clamp(y, dt * vy * ih, ny, cy, fy);
         cell_clamp(z, dt * vz * ih, nz, cz, fz);
-        const int wx = cx - (x0 - kBH), wy = cy - (y0 - kBH);
-        if (wx >= 0 && wx + 1 < kBXH && wy >= 0 && wy + 1 < kBYH && cz >= z - kBH &&
-            cz + 1 <= z + kBH) {
-          const int za = cz % kBRing, zb = (cz + 1) % kBRing;
-          float gv[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            gv[c] = lerp8(su[c][za][wy][wx], su[c][za][wy][wx + 1], su[c][za][wy + 1][wx],
-                          su[c][za][wy + 1][wx + 1], su[c][zb][wy][wx], su[c][zb][wy][wx + 1],
-                          su[c][zb][wy + 1][wx], su[c][zb][wy + 1][wx + 1], fx, fy, fz);
-          ux += gv[0];
-          uy += gv[1];
-          uz += gv[2];
-        } else {
+        float gv[3];
+        if (!mu.sample3(tt.x0, tt.y0, z, cx, cy, cz, fx, fy, fz, gv)) {
           const Cell cl = make_cell_clamp(g, x, y, z, dt * vx * ih, dt * vy * ih, dt * vz * ih);
-          ux += sample(N0, cl);
-          uy += sample(N1, cl);
-          uz += sample(N2, cl);
+          gv[0] = sample(N0, cl);
+          gv[1] = sample(N1, cl);
+          gv[2] = sample(N2, cl);
         }
+        ux += gv[0];
+        uy += gv[1];
+        uz += gv[2];
         bst(C0, i, ux);
         bst(C1, i, uy);
         bst(C2, i, uz);
@@ -542,7 +579,6 @@ __global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a, BwdTiling
       mind = fmin(mind, (double)det);
       const Cell czc = make_cell_zero(g, x, y, z, ucen[0] * ih, ucen[1] * ih, ucen[2] * ih);
       const int j0 = z % 3, jm = (z + 2) % 3, jp = (z + 1) % 3;
-      const int jx = tx + 1, jy = ty + 1;
       float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -560,9 +596,32 @@ __global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a, BwdTiling
     __syncthreads();
   }
   const double m = block_min(mind);
-  if (threadIdx.x == 0) a.partDet[blockIdx.x] = m;
-  (void)sy;
-  (void)sz;
+  if (threadIdx.x == 0) a.partDet[block] = m;
+}
+
+template <int NC, bool HAS_U>
+__global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a) {
+  backward_staged_body<NC, HAS_U>(a, blockIdx.x);
+}
+
+// Batched body-force step: every problem gets backward_partials(g) blocks and
+// runs the staged body when its grid allows it.
+template <int NC, bool HAS_U>
+__global__ __launch_bounds__(kBlock) void k_backward_force_batched(BatchRef br, int slot) {
+  const int p = batch_pair(br, blockIdx.x);
+  const BwdArgs& a = ((const PairTab*)br.tab[p])->bwd[slot];
+  const int tile = blockIdx.x - br.off[p];
+  if (sweep_staged(a.g))
+    backward_staged_body<NC, HAS_U>(a, tile);
+  else
+    backward_body<NC, HAS_U, false, true>(a, tile, br.off[p + 1] - br.off[p]);
+}
+
+void launch_forward(const FwdArgs& a, hipStream_t s) {
+  if (a.nch == 2)
+    fwd_dispatch<2>(a, s);
+  else
+    fwd_dispatch<1>(a, s);
 }
 
 template <int NC>
@@ -581,19 +640,18 @@ static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
 
 void launch_backward(const BwdArgs& a, hipStream_t s) {
   const bool hu = a.j >= 0, uz = (a.u_next == nullptr), hb = (a.jb >= 0 && a.jb < a.T);
-  if (hb && !uz && bwd_staged(a.g)) {
-    const BwdTiling t = bwd_tiling(a.g);
-    const dim3 grid(t.ntx * t.nty * t.nslab);
+  if (hb && !uz && sweep_staged(a.g)) {
+    const dim3 grid(backward_partials(a.g));
     if (a.nch == 2) {
       if (hu)
-        hipLaunchKernelGGL((k_backward_staged<2, true>), grid, dim3(kBlock), 0, s, a, t);
+        hipLaunchKernelGGL((k_backward_staged<2, true>), grid, dim3(kBlock), 0, s, a);
       else
-        hipLaunchKernelGGL((k_backward_staged<2, false>), grid, dim3(kBlock), 0, s, a, t);
+        hipLaunchKernelGGL((k_backward_staged<2, false>), grid, dim3(kBlock), 0, s, a);
     } else {
       if (hu)
-        hipLaunchKernelGGL((k_backward_staged<1, true>), grid, dim3(kBlock), 0, s, a, t);
+        hipLaunchKernelGGL((k_backward_staged<1, true>), grid, dim3(kBlock), 0, s, a);
       else
-        hipLaunchKernelGGL((k_backward_staged<1, false>), grid, dim3(kBlock), 0, s, a, t);
+        hipLaunchKernelGGL((k_backward_staged<1, false>), grid, dim3(kBlock), 0, s, a);
     }
     return;
   }
@@ -607,7 +665,8 @@ void launch_backward(const BwdArgs& a, hipStream_t s) {
 void launch_forward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s) {
   const bool first = (j == 0), last = (j == T - 1);
   const dim3 grid(br.off[br.np]);
-#define FWDB(NC, F, L) hipLaunchKernelGGL((k_forward_batched<NC, F, L>), grid, dim3(kBlock), 0, s, br, j)
+#define FWDB(NC, F, L) \
+  hipLaunchKernelGGL((k_forward_batched<NC, F, L>), grid, dim3(kBlock), 0, s, br, j)
   if (nch == 2) {
     if (first && last) FWDB(2, true, true); else if (first) FWDB(2, true, false);
     else if (last) FWDB(2, false, true); else FWDB(2, false, false);
@@ -625,18 +684,21 @@ void launch_backward_batched(const BatchRef& br, int j, int T, int nch, hipStrea
   const int slot = j + 1;
 #define BWDB(NC, A, B, C) \
   hipLaunchKernelGGL((k_backward_batched<NC, A, B, C>), grid, dim3(kBlock), 0, s, br, slot)
+#define BWDF(NC, A) \
+  hipLaunchKernelGGL((k_backward_force_batched<NC, A>), grid, dim3(kBlock), 0, s, br, slot)
   if (nch == 2) {
     if (hu && uz && !hb) BWDB(2, true, true, false);
-    else if (hu && !uz && hb) BWDB(2, true, false, true);
+    else if (hu && !uz && hb) BWDF(2, true);
     else if (hu && !uz && !hb) BWDB(2, true, false, false);
-    else if (!hu && hb) BWDB(2, false, false, true);
+    else if (!hu && hb) BWDF(2, false);
   } else {
     if (hu && uz && !hb) BWDB(1, true, true, false);
-    else if (hu && !uz && hb) BWDB(1, true, false, true);
+    else if (hu && !uz && hb) BWDF(1, true);
     else if (hu && !uz && !hb) BWDB(1, true, false, false);
-    else if (!hu && hb) BWDB(1, false, false, true);
+    else if (!hu && hb) BWDF(1, false);
   }
 #undef BWDB
+#undef BWDF
 }
 
 // ------------------------------------------------------------ utilities ----

@@ -211,7 +211,8 @@ void set_fft_x_elems(int elems);
 void set_fft_cols(int axis, int cols);   // axis 0: y tiles, 1: z tiles
 void launch_forward(const FwdArgs& a, hipStream_t s);
 void launch_backward(const BwdArgs& a, hipStream_t s);
-// Number of min-det partials a body-force launch of launch_backward writes.
+// Blocks of a body-force launch of the backward sweep on this grid = the min-det
+// partials it writes (single or batched).  Forward launches use reduce_grid.
 int backward_partials(const Geom& g);
 void launch_forward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);
 void launch_backward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);

@@ -826,6 +826,7 @@ static void build_pairtab(Ctx& c, int li, PairTab* t) {
   FftLaunch Lf;
   t->fft = make_fft(c, li, MODE_GRAD, &Lf);
   const int nb = reduce_grid(n);
+  const int nbw = backward_partials(L.g);
   const double h = (double)L.g.h;
   for (int init = 0; init < 2; ++init) {
     DecideArgs& d = t->dec[init];
@@ -836,7 +837,7 @@ static void build_pairtab(Ctx& c, int li, PairTab* t) {
     d.partDet = c.partDet;
     d.T = k.T;
     d.nfw = nb;
-    d.nbw = nb;
+    d.nbw = nbw;
     d.has_img = k.C > 1;
     d.guard = c.guard;
     d.init = init;
@@ -901,7 +902,7 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
   for (int p = 0; p < n; ++p) dtabs[p] = cs[p].ptab;
   for (int li = 0; li < L; ++li) {
     BatchPlan bp{};
-    std::vector<int> tf(n), tx(n), ty(n), tz(n), tr(n), one(n, 1);
+    std::vector<int> tf(n), tb(n), tx(n), ty(n), tz(n), tr(n), one(n, 1);
     for (int p = 0; p < n; ++p) {
       Ctx& c = cs[p];
       const Config& k = c.cfg;
@@ -921,6 +922,7 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
       FftPair tmp = make_fft(c, li, MODE_GRAD, &Lf);
       (void)tmp;
       tf[p] = reduce_grid(lv.g.n);
+      tb[p] = backward_partials(lv.g);
       tx[p] = Lf.x_tiles;
       ty[p] = Lf.y_tiles;
       tz[p] = Lf.z_tiles;
@@ -934,7 +936,7 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
       bp.zl = std::max(bp.zl, Lf.z_lds);
     }
     batch_offsets(bp.fwd, n, tf.data(), dtabs.data());
-    bp.bwd = bp.fwd;
+    batch_offsets(bp.bwd, n, tb.data(), dtabs.data());
     batch_offsets(bp.fx, n, tx.data(), dtabs.data());
     bp.fxi = bp.fx;
     batch_offsets(bp.fy, n, ty.data(), dtabs.data());
