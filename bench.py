@@ -201,6 +201,70 @@ def stored_traffic(kernel):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
+# Calibration: the copy of the finest-level velocity buffer between pyramid levels
+# (k_copy of 3 T |P| floats) reads and writes exactly this many bytes.
+COPY_FLOATS = 3 * T * 280 * 160 * 240
+FINEST_VOXELS = 280 * 160 * 240
+
+
+def compute_traffic(fetch_db, write_db, out_path):
+    """Bytes per finest-level launch of the forward and backward sweep classes from two
+    rocprofv3 counter runs of the bench command (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what that counter reads for the copy kernel of known size."""
+    import re
+    from collections import defaultdict
+
+    def per_kernel(db, counter):
+        rows = defaultdict(list)
+        for name, grid, dur, cn, val in _kernel_rows(db):
+            if cn == counter:
+                rows[(name, grid)].append((dur, val))
+        return rows
+
+    out = {"source_sha": library_sources_sha(), "grid": [280, 160, 240],
+           "calibration": f"k_copy of the finest-level velocity ({COPY_FLOATS} floats = "
+                          f"{4 * COPY_FLOATS} bytes read and written)", "kernels": {}}
+    factors = {}
+    per = {}
+    for tag, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        rows = per_kernel(db, counter)
+        copy = [v for (name, grid), items in rows.items() if name == "k_copy" and grid == COPY_FLOATS
+                for d, v in items]
+        if not copy:
+            raise SystemExit(f"no finest-level k_copy dispatch in {db}")
+        factors[tag] = 4.0 * COPY_FLOATS / (1024.0 * sum(copy) / len(copy))
+        per[tag] = rows
+    out["fetch_factor"], out["write_factor"] = factors["fetch"], factors["write"]
+    # finest-level dispatches of each class: the longest launch-shape group per variant
+    classes = {"forward": r"^void k_forward<", "backward": r"^void k_backward(_staged)?<"}
+    for cls, pat in classes.items():
+        tot = {"fetch": [], "write": []}
+        durs = []
+        for tag in ("fetch", "write"):
+            for (name, grid), items in per[tag].items():
+                if not re.match(pat, name):
+                    continue
+                for sub, part in _split_levels([(d, v) for d, v in items]):
+                    if sub == " (short)":
+                        continue
+                    if len({g for (n2, g) in per[tag] if n2 == name}) > 1 and grid != max(
+                            g for (n2, g) in per[tag] if n2 == name):
+                        continue
+                    tot[tag] += [v * 1024.0 * factors[tag] for d, v in part]
+                    if tag == "fetch":
+                        durs += [d for d, v in part]
+        if tot["fetch"] and tot["write"]:
+            f = sum(tot["fetch"]) / len(tot["fetch"])
+            w = sum(tot["write"]) / len(tot["write"])
+            out["kernels"][cls] = {"launches": len(tot["fetch"]), "fetch_bytes": f, "write_bytes": w,
+                                   "fetch_bytes_per_voxel": f / FINEST_VOXELS,
+                                   "write_bytes_per_voxel": w / FINEST_VOXELS,
+                                   "mean_us_under_counters": sum(durs) / len(durs) / 1e3}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out["kernels"], indent=1))
+
+
 BATCH_ITERS = 100
 
 
@@ -307,7 +371,12 @@ def main():
                          "uneven pairs in one grouped launch sequence vs 16 sequential runs")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("DB", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 database and exit")
+    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "OUT"),
+                    help="compute calibrated per-launch sweep traffic from two counter runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        compute_traffic(*args.traffic_from)
+        return
     if args.summarize_profile:
         summarize_profile(*args.summarize_profile)
         return
