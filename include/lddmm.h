@@ -215,7 +215,10 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * passes of K holds in LDS (row pairs per block = value / (3 nx), 1..8; clamped
  * to [256, 8192]; default 2048).  LDDMM_TUNE_FFT_COLS / LDDMM_TUNE_FFT_ZCOLS:
  * kx columns per tile of the y / the z pass (rounded down to a power of two in
- * [2, 32], then halved while columns x length exceeds 4096; defaults 16 and 8).  Sweep-block counts change
+ * [2, 32], then halved while columns x length exceeds 4096; defaults 16 and 8).
+ * LDDMM_TUNE_STAGED_MIN_BLOCKS: the backward sweep uses its LDS-staged kernel
+ * on grids that give at least this many blocks (one per 32 x 8 column and
+ * z-slab; default 2048, at most 4096 blocks).  Sweep-block counts change
  * only the order of the FP64 energy partial sums.  A value applies to calls
  * enqueued after it is set.  Returns LDDMM_OK or LDDMM_EINVAL (unknown `which`
  * or value < 1).
@@ -224,6 +227,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 #define LDDMM_TUNE_FFT_X_ELEMS  1
 #define LDDMM_TUNE_FFT_COLS     2
 #define LDDMM_TUNE_FFT_ZCOLS    3
+#define LDDMM_TUNE_STAGED_MIN_BLOCKS 4
 int lddmm_set_tunable(int32_t which, int32_t value);
 
 /* Human-readable text of a status code (static storage). */

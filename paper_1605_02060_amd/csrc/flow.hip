@@ -345,16 +345,25 @@ __host__ __device__ inline SweepTiling sweep_tiling(const Geom& g) {
   return t;
 }
 
-// The staged kernel runs when its blocks fit the partial buffer and every byte
-// offset into a map (3 n floats) fits 32 bits.
-__host__ __device__ inline bool sweep_staged(const Geom& g) {
+// The staged kernel runs when it has at least g_staged_min_blocks blocks (default
+// 8 per CU: a block marches a whole slab, so fewer leave the chip idle -- at
+// 140 x 80 x 120 it has 400 blocks and ran 1.7x slower than the grid-stride
+// kernel), when its blocks fit the partial buffer, and when every byte offset
+// into a map (3 n floats) fits 32 bits.  The host decides and passes the
+// decision in BwdArgs::staged.
+static int g_staged_min_blocks = 2048;
+
+void set_staged_min_blocks(int b) { g_staged_min_blocks = b < 1 ? 1 : b; }
+
+bool backward_staged(const Geom& g) {
   const SweepTiling t = sweep_tiling(g);
-  return (long long)t.ntx * t.nty * t.nslab <= kPartMax && 3LL * g.n < (1LL << 30);
+  const long long blocks = (long long)t.ntx * t.nty * t.nslab;
+  return blocks >= g_staged_min_blocks && blocks <= kPartMax && 3LL * g.n < (1LL << 30);
 }
 
 // Blocks (and min-det partials) of one body-force launch of this grid.
 int backward_partials(const Geom& g) {
-  if (!sweep_staged(g)) return reduce_grid(g.n);
+  if (!backward_staged(g)) return reduce_grid(g.n);
   const SweepTiling t = sweep_tiling(g);
   return t.ntx * t.nty * t.nslab;
 }
@@ -611,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_force_batched(BatchRef br, 
   const int p = batch_pair(br, blockIdx.x);
   const BwdArgs& a = ((const PairTab*)br.tab[p])->bwd[slot];
   const int tile = blockIdx.x - br.off[p];
-  if (sweep_staged(a.g))
+  if (a.staged)
     backward_staged_body<NC, HAS_U>(a, tile);
   else
     backward_body<NC, HAS_U, false, true>(a, tile, br.off[p + 1] - br.off[p]);
@@ -640,7 +649,7 @@ static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
 
 void launch_backward(const BwdArgs& a, hipStream_t s) {
   const bool hu = a.j >= 0, uz = (a.u_next == nullptr), hb = (a.jb >= 0 && a.jb < a.T);
-  if (hb && !uz && sweep_staged(a.g)) {
+  if (hb && !uz && a.staged) {
     const dim3 grid(backward_partials(a.g));
     if (a.nch == 2) {
       if (hu)

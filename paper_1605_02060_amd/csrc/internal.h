@@ -118,6 +118,7 @@ struct BwdArgs {
   double* partDet;        // [kPartMax] min det per block
   const State* st;
   int need_mode;          // run only when st->mode == need_mode (-1: always)
+  int staged;             // body-force steps run the LDS-staged kernel (backward_staged)
 };
 
 // x-inverse pass epilogue
@@ -214,6 +215,8 @@ void launch_backward(const BwdArgs& a, hipStream_t s);
 // Blocks of a body-force launch of the backward sweep on this grid = the min-det
 // partials it writes (single or batched).  Forward launches use reduce_grid.
 int backward_partials(const Geom& g);
+bool backward_staged(const Geom& g);
+void set_staged_min_blocks(int blocks);
 void launch_forward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);
 void launch_backward_batched(const BatchRef& br, int j, int T, int nch, hipStream_t s);
 void launch_crop3(const float* u, const Geom& g, int Nx, int Ny, int Nz, float* out,

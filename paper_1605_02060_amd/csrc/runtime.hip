@@ -455,6 +455,7 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
     a.partDet = c.partDet + (long long)(a.jb >= 0 ? a.jb : 0) * kPartMax;
     a.st = c.st;
     a.need_mode = need_mode;
+    a.staged = backward_staged(L.g);
     if (a.j < 0 && a.jb < 0) continue;
     {
       ProfScope ps(LDDMM_PROF_BACKWARD, n, s);
@@ -813,6 +814,7 @@ static void build_pairtab(Ctx& c, int li, PairTab* t) {
     a.partDet = c.partDet + (long long)(a.jb >= 0 ? a.jb : 0) * kPartMax;
     a.st = c.st;
     a.need_mode = MODE_GRAD;
+    a.staged = backward_staged(L.g);
   }
   for (int j = 0; j < k.T; ++j) {
     UpdArgs& u = t->upd[j];
@@ -1146,6 +1148,11 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
   if (which == LDDMM_TUNE_SWEEP_BLOCKS) {
     if (value < 1) return LDDMM_EINVAL;
     set_sweep_blocks(value);
+    return LDDMM_OK;
+  }
+  if (which == LDDMM_TUNE_STAGED_MIN_BLOCKS) {
+    if (value < 1) return LDDMM_EINVAL;
+    set_staged_min_blocks(value);
     return LDDMM_OK;
   }
   if (which == LDDMM_TUNE_FFT_X_ELEMS) {

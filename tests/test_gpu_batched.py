@@ -37,23 +37,31 @@ def _pairs(shapes, seed0=400, with_img=True):
     return out
 
 
-@pytest.mark.parametrize("guard,levels,iters", [(True, 2, (6, 5)), (False, 1, (5,))])
-def test_batched_equals_single_calls(guard, levels, iters):
-    say(f"batched vs single guard={guard} levels={levels}")
+@pytest.mark.parametrize("guard,levels,iters,staged", [(True, 2, (6, 5), False),
+                                                       (False, 1, (5,), False),
+                                                       (True, 2, (6, 5), True)])
+def test_batched_equals_single_calls(guard, levels, iters, staged):
+    # staged: force the LDS-staged backward kernel on these small grids
+    say(f"batched vs single guard={guard} levels={levels} staged={staged}")
     shapes = [(20, 24, 28), (32, 32, 32), (18, 30, 22), (26, 20, 34)]
     pairs = _pairs(shapes)
     prm = L.Params(T=5, n_levels=levels, iters=iters, step=0.05 if guard else 0.02, guard=guard,
                    weight=(1.0, 0.3))
-    res, code = L.lddmm_register_batched([d for _, d in pairs], prm)
-    torch.cuda.synchronize()
-    for (p, d), r in zip(pairs, res):
-        single = L.lddmm_register(d["M0"], d["M1"], d["MI0"], d["MI1"], params=prm,
-                                  spacing=d["spacing"])
+    L.lddmm_set_tunable(L.TUNE_STAGED_MIN_BLOCKS, 1 if staged else 2048)
+    try:
+        res, code = L.lddmm_register_batched([d for _, d in pairs], prm)
         torch.cuda.synchronize()
-        assert r["status"] == single["status"]
-        assert torch.equal(r["v"], single["v"])
-        assert torch.equal(r["phi10"], single["phi10"]) and torch.equal(r["phi01"], single["phi01"])
-        assert torch.equal(r["trace"].nan_to_num(-1.0), single["trace"].nan_to_num(-1.0))
+        for (p, d), r in zip(pairs, res):
+            single = L.lddmm_register(d["M0"], d["M1"], d["MI0"], d["MI1"], params=prm,
+                                      spacing=d["spacing"])
+            torch.cuda.synchronize()
+            assert r["status"] == single["status"]
+            assert torch.equal(r["v"], single["v"])
+            assert torch.equal(r["phi10"], single["phi10"])
+            assert torch.equal(r["phi01"], single["phi01"])
+            assert torch.equal(r["trace"].nan_to_num(-1.0), single["trace"].nan_to_num(-1.0))
+    finally:
+        L.lddmm_set_tunable(L.TUNE_STAGED_MIN_BLOCKS, 2048)
 
 
 def test_batched_matches_oracle_for_each_problem():
