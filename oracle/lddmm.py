@@ -23,7 +23,8 @@ CLARITY Brains to an Atlas via Masked LDDMM", SPIE 9896, 2016):
   nearest-neighbour interpolation.
 
 Readings where the paper is silent (each listed in the design doc):
-* flow integrated semi-Lagrangian, first order, T intervals, dt = 1/T;
+* flow integrated semi-Lagrangian, first order, T intervals, dt = 1/T (or
+  with fourth-order Runge-Kutta departure points, the paper's integrator);
 * maps stored as displacements u = phi - id in physical units;
 * displacements sampled with clamped coordinates, images with zero outside;
 * derivatives by the np.gradient stencil (central inside, one-sided faces);
@@ -364,6 +365,7 @@ class Params:
     guard: bool = True
     weight: tuple = (1.0, 0.0)      # (mask channel, masked-image channel)
     spacing: float = 1.0            # h at the finest level (physical units per voxel)
+    integrator: str = "euler"       # departure points: "euler" or "rk4" (the paper's)
 
 
 @dataclass
@@ -388,11 +390,37 @@ class Problem:
 # One level: forward sweep, energy, backward sweep, gradients
 # ---------------------------------------------------------------------------
 
-def forward_sweep(v, J0, h, weighted):
+def step_velocity(vj, h, dt, sign, integrator):
+    """Mean velocity over one step along the characteristic of the (time-constant
+    within the step) field v_j through each grid point x, followed forward
+    (sign = +1) or backward (sign = -1) in time for dt.  The departure / arrival
+    point is y = x + sign dt vbar / h.
+
+    euler: vbar = v_j(x).
+    rk4  : the classical fourth-order Runge-Kutta steps of dy/ds = sign v_j(y)/h,
+           with v_j sampled trilinearly (clamped coordinates) between grid points:
+           k1 = v_j(x), k2 = v_j(x + sign dt/2 k1/h), k3 = v_j(x + sign dt/2 k2/h),
+           k4 = v_j(x + sign dt k3/h), vbar = (k1 + 2 k2 + 2 k3 + k4) / 6.
+    The paper integrates the flow with fourth-order Runge-Kutta (Methods,
+    Registration); the first-order step is the semi-Lagrangian default here."""
+    if integrator == "euler":
+        return vj
+    if integrator != "rk4":
+        raise ValueError(integrator)
+    X = index_positions(vj.shape[1:])
+    k1 = vj
+    k2 = sample_clamp_vec(vj, X + sign * 0.5 * dt * k1 / h)
+    k3 = sample_clamp_vec(vj, X + sign * 0.5 * dt * k2 / h)
+    k4 = sample_clamp_vec(vj, X + sign * dt * k3 / h)
+    return (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0
+
+
+def forward_sweep(v, J0, h, weighted, integrator="euler"):
     """Flow of the inverse maps and the deformed templates.
 
-    u0[0] = 0;  u0[j+1](x) = -dt v_j(x) + S_clamp(u0[j]; x - dt v_j(x)/h)
-    (semi-Lagrangian step of d/dt phi_t0 + D phi_t0 v_t = 0), and
+    u0[0] = 0;  u0[j+1](x) = -dt vbar_j(x) + S_clamp(u0[j]; x - dt vbar_j(x)/h)
+    (semi-Lagrangian step of d/dt phi_t0 + D phi_t0 v_t = 0; vbar_j = v_j(x) for
+    the first-order step, see step_velocity), and
     J0t[c][j](x) = S_zero(J0[c]; x + u0[j](x)/h) for weighted channels c.
     Returns (u0 list of T+1 fields, J0t dict c -> list of T+1 fields).
     """
@@ -404,16 +432,18 @@ def forward_sweep(v, J0, h, weighted):
     u0 = [u]
     J0t = {c: [J0[c].copy()] for c in weighted}
     for j in range(T):
-        y = X - dt * v[j] / h
-        u = -dt * v[j] + sample_clamp_vec(u, y)
+        vbar = step_velocity(v[j], h, dt, -1.0, integrator)
+        y = X - dt * vbar / h
+        u = -dt * vbar + sample_clamp_vec(u, y)
         u0.append(u)
         for c in weighted:
             J0t[c].append(sample_zero(J0[c], X + u / h))
     return u0, J0t
 
 
-def backward_maps(v, h):
-    """u1[T] = 0;  u1[j](x) = dt v_j(x) + S_clamp(u1[j+1]; x + dt v_j(x)/h)  (phi_{t,1} - id)."""
+def backward_maps(v, h, integrator="euler"):
+    """u1[T] = 0;  u1[j](x) = dt vbar_j(x) + S_clamp(u1[j+1]; x + dt vbar_j(x)/h)
+    (phi_{t,1} - id; vbar_j as in step_velocity, followed forward in time)."""
     T = v.shape[0]
     dt = 1.0 / T
     shape = v.shape[2:]
@@ -422,7 +452,8 @@ def backward_maps(v, h):
     u1 = [None] * (T + 1)
     u1[T] = u
     for j in range(T - 1, -1, -1):
-        u = dt * v[j] + sample_clamp_vec(u, X + dt * v[j] / h)
+        vbar = step_velocity(v[j], h, dt, 1.0, integrator)
+        u = dt * vbar + sample_clamp_vec(u, X + dt * vbar / h)
         u1[j] = u
     return u1
 
@@ -438,7 +469,7 @@ def energy_terms(v, J0, J1, prm: Params, h):
         nan = float("nan")
         return {"E": nan, "R": nan, "D": nan, "img_ssd": nan, "u0": None, "J0t": None,
                 "r": None, "weighted": weighted}
-    u0, J0t = forward_sweep(v, J0, h, weighted)
+    u0, J0t = forward_sweep(v, J0, h, weighted, prm.integrator)
     T = v.shape[0]
     X = index_positions(v.shape[2:])
     R = reg_energy(v, prm.alpha, prm.gamma, h)
@@ -465,7 +496,7 @@ def gradient_V(v, st, prm: Params, h):
     """
     T = v.shape[0]
     X = index_positions(v.shape[2:])
-    u1 = backward_maps(v, h)
+    u1 = backward_maps(v, h, prm.integrator)
     g = np.zeros_like(v)
     min_det = math.inf
     for j in range(T - 1, -1, -1):
@@ -655,7 +686,7 @@ def register(problem: Problem, prm: Params, v_init=None):
                       levels=grids)
     h = prm.spacing * grids[-1]["h"]
     st = energy_terms(v, pyr0[-1], pyr1[-1], prm, h)
-    u1 = backward_maps(v, h)
+    u1 = backward_maps(v, h, prm.integrator)
     phi10 = st["u0"][T][:, :nz, :ny, :nx]
     phi01 = u1[0][:, :nz, :ny, :nx]
     if status == STATUS_OK and worst_det <= 0.0:
@@ -691,6 +722,8 @@ def gradient(problem: Problem, prm: Params, v, kind="V"):
     if kind == "V":
         g, md = gradient_V(v, st, prm, h)
         return g, st, md
+    if prm.integrator != "euler":
+        raise ValueError("the exact gradient is defined for the first-order step only")
     return gradient_L2(v, st, prm, h, J0), st, math.nan
 
 
