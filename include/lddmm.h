@@ -67,6 +67,14 @@ extern "C" {
 
 /* flags */
 #define LDDMM_FLAG_RECOMPUTE_PHI 1   /* exact gradient: recompute phi_t from checkpoints */
+#define LDDMM_FLAG_RK4           2   /* maps by fourth-order Runge-Kutta departure points
+                                        (the paper's integrator, Methods, Registration):
+                                        along each step's characteristic, v_j sampled at the
+                                        RK4 stages, vbar = (k1 + 2 k2 + 2 k3 + k4)/6 replaces
+                                        v_j(x) in both sweeps.  Single-problem calls only
+                                        (lddmm_register_batched returns LDDMM_EINVAL), and
+                                        lddmm_gradient kind LDDMM_GRAD_L2 (exact reverse mode
+                                        of the first-order step) returns LDDMM_EINVAL. */
 
 /* User grid N (voxels) and the voxel spacing h of the finest level. */
 typedef struct {

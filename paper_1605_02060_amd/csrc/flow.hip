@@ -105,9 +105,30 @@ void launch_up2(const float* src, const Geom& coarse, float* dst, const Geom& fi
                      fine, nfields);
 }
 
+// Mean velocity over one step along the characteristic through grid point
+// (x, y, z), with v_j constant in time within the step: the fourth-order
+// Runge-Kutta stages of dy/ds = v_j(y) / h taken over the signed step s = +-dt/h
+// (k1 = v_j(x), k2 = v_j(x + s/2 k1), k3 = v_j(x + s/2 k2), k4 = v_j(x + s k3),
+// trilinear with clamped coordinates), vbar = (k1 + 2 k2 + 2 k3 + k4) / 6.  The
+// departure or arrival point is then x + s vbar (the paper's flow integrator).
+__device__ __forceinline__ void rk4_mean(rsrc_t V0, rsrc_t V1, rsrc_t V2, const Geom& g, int x,
+                                         int y, int z, float s, float& mx, float& my, float& mz) {
+  const float k1x = mx, k1y = my, k1z = mz;
+  const Cell c2 = make_cell_clamp(g, x, y, z, 0.5f * s * k1x, 0.5f * s * k1y, 0.5f * s * k1z);
+  const float k2x = sample(V0, c2), k2y = sample(V1, c2), k2z = sample(V2, c2);
+  const Cell c3 = make_cell_clamp(g, x, y, z, 0.5f * s * k2x, 0.5f * s * k2y, 0.5f * s * k2z);
+  const float k3x = sample(V0, c3), k3y = sample(V1, c3), k3z = sample(V2, c3);
+  const Cell c4 = make_cell_clamp(g, x, y, z, s * k3x, s * k3y, s * k3z);
+  const float k4x = sample(V0, c4), k4y = sample(V1, c4), k4z = sample(V2, c4);
+  const float sixth = 1.f / 6.f;
+  mx = (k1x + 2.f * k2x + 2.f * k3x + k4x) * sixth;
+  my = (k1y + 2.f * k2y + 2.f * k3y + k4y) * sixth;
+  mz = (k1z + 2.f * k2z + 2.f * k3z + k4z) * sixth;
+}
+
 // ---------------------------------------------------------- forward sweep ----
 
-template <int NC, bool FIRST, bool LAST>
+template <int NC, bool FIRST, bool LAST, bool RK4 = false>
 __device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, uint32_t ntiles) {
   const State* st = a.st;
   if (st->mode == MODE_STOPPED) return;
@@ -136,9 +157,11 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, ui
     int x, y, z;
     vcoord(g, i, x, y, z);
     const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
-    float ux = -dt * vx, uy = -dt * vy, uz = -dt * vz;
+    float mx = vx, my = vy, mz = vz;                    // velocity of the map step
+    if (RK4) rk4_mean(V0, V1, V2, g, x, y, z, -dt * ih, mx, my, mz);
+    float ux = -dt * mx, uy = -dt * my, uz = -dt * mz;
     if (!FIRST) {
-      const Cell cl = make_cell_clamp(g, x, y, z, -dt * vx * ih, -dt * vy * ih, -dt * vz * ih);
+      const Cell cl = make_cell_clamp(g, x, y, z, -dt * mx * ih, -dt * my * ih, -dt * mz * ih);
       ux += sample(U0, cl);
       uy += sample(U1, cl);
       uz += sample(U2, cl);
@@ -187,9 +210,9 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, ui
   }
 }
 
-template <int NC, bool FIRST, bool LAST>
+template <int NC, bool FIRST, bool LAST, bool RK4>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
-  forward_body<NC, FIRST, LAST>(a, blockIdx.x, gridDim.x);
+  forward_body<NC, FIRST, LAST, RK4>(a, blockIdx.x, gridDim.x);
 }
 
 // One launch for every problem of a batch: block b runs tile b - off[p] of problem p.
@@ -200,25 +223,25 @@ __global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) 
   forward_body<NC, FIRST, LAST>(t->fwd[j], blockIdx.x - br.off[p], br.off[p + 1] - br.off[p]);
 }
 
-template <int NC>
+template <int NC, bool RK4>
 static void fwd_dispatch(const FwdArgs& a, hipStream_t s) {
   const int grid = reduce_grid(a.g.n);
   const bool first = (a.j == 0), last = (a.j == a.T - 1);
   if (first && last)
-    hipLaunchKernelGGL((k_forward<NC, true, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<NC, true, true, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
   else if (first)
-    hipLaunchKernelGGL((k_forward<NC, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<NC, true, false, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
   else if (last)
-    hipLaunchKernelGGL((k_forward<NC, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<NC, false, true, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((k_forward<NC, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<NC, false, false, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 
 
 // --------------------------------------------------------- backward sweep ----
 
-template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
+template <int NC, bool HAS_U, bool UZERO, bool HAS_B, bool RK4 = false>
 __device__ __forceinline__ void backward_body(const BwdArgs& a, uint32_t tile, uint32_t ntiles) {
   const State* st = a.st;
   if (a.need_mode >= 0 && st->mode != a.need_mode) return;
@@ -247,7 +270,8 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, uint32_t tile, u
     int x, y, z;
     vcoord(g, i, x, y, z);
     if (HAS_U) {
-      const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
+      float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
+      if (RK4) rk4_mean(V0, V1, V2, g, x, y, z, dt * ih, vx, vy, vz);   // vbar replaces v_j(x)
       float ux = dt * vx, uy = dt * vy, uz = dt * vz;
       if (!UZERO) {
         const Cell cl = make_cell_clamp(g, x, y, z, dt * vx * ih, dt * vy * ih, dt * vz * ih);
@@ -298,9 +322,9 @@ __device__ __forceinline__ void backward_body(const BwdArgs& a, uint32_t tile, u
   }
 }
 
-template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
+template <int NC, bool HAS_U, bool UZERO, bool HAS_B, bool RK4>
 __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
-  backward_body<NC, HAS_U, UZERO, HAS_B>(a, blockIdx.x, gridDim.x);
+  backward_body<NC, HAS_U, UZERO, HAS_B, RK4>(a, blockIdx.x, gridDim.x);
 }
 
 template <int NC, bool HAS_U, bool UZERO, bool HAS_B>
@@ -627,24 +651,31 @@ __global__ __launch_bounds__(kBlock) void k_backward_force_batched(BatchRef br, 
 }
 
 void launch_forward(const FwdArgs& a, hipStream_t s) {
-  if (a.nch == 2)
-    fwd_dispatch<2>(a, s);
-  else
-    fwd_dispatch<1>(a, s);
+  if (a.rk4) {
+    if (a.nch == 2)
+      fwd_dispatch<2, true>(a, s);
+    else
+      fwd_dispatch<1, true>(a, s);
+  } else {
+    if (a.nch == 2)
+      fwd_dispatch<2, false>(a, s);
+    else
+      fwd_dispatch<1, false>(a, s);
+  }
 }
 
-template <int NC>
+template <int NC, bool RK4>
 static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
   const int grid = reduce_grid(a.g.n);
   const bool hu = a.j >= 0, uz = (a.u_next == nullptr), hb = (a.jb >= 0 && a.jb < a.T);
   if (hu && uz && !hb)
-    hipLaunchKernelGGL((k_backward<NC, true, true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_backward<NC, true, true, false, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
   else if (hu && !uz && hb)
-    hipLaunchKernelGGL((k_backward<NC, true, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_backward<NC, true, false, true, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
   else if (hu && !uz && !hb)
-    hipLaunchKernelGGL((k_backward<NC, true, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_backward<NC, true, false, false, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
   else if (!hu && hb)
-    hipLaunchKernelGGL((k_backward<NC, false, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_backward<NC, false, false, true, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 void launch_backward(const BwdArgs& a, hipStream_t s) {
@@ -664,10 +695,17 @@ void launch_backward(const BwdArgs& a, hipStream_t s) {
     }
     return;
   }
-  if (a.nch == 2)
-    bwd_dispatch<2>(a, s);
-  else
-    bwd_dispatch<1>(a, s);
+  if (a.rk4) {
+    if (a.nch == 2)
+      bwd_dispatch<2, true>(a, s);
+    else
+      bwd_dispatch<1, true>(a, s);
+  } else {
+    if (a.nch == 2)
+      bwd_dispatch<2, false>(a, s);
+    else
+      bwd_dispatch<1, false>(a, s);
+  }
 }
 
 // Batched sweeps: step j of every problem (same T, same channel count).

@@ -95,6 +95,7 @@ struct FwdArgs {
   double* partD;          // [kPartMax]
   double* partI;          // [kPartMax]
   const State* st;
+  int rk4;                // departure points by fourth-order Runge-Kutta
 };
 
 struct BwdArgs {
@@ -119,6 +120,7 @@ struct BwdArgs {
   const State* st;
   int need_mode;          // run only when st->mode == need_mode (-1: always)
   int staged;             // body-force steps run the LDS-staged kernel (backward_staged)
+  int rk4;                // departure points by fourth-order Runge-Kutta
 };
 
 // x-inverse pass epilogue

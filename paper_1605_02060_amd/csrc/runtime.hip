@@ -130,6 +130,7 @@ struct Config {
   Level lv[LDDMM_MAX_LEVELS];
   int rows;
   int ck;            // exact gradient: checkpoint spacing (0 = keep every u0_j)
+  int rk4;           // departure points by fourth-order Runge-Kutta (LDDMM_FLAG_RK4)
 };
 
 // u0 storage of the exact gradient.  Without recompute slot j holds u0_j.  With
@@ -214,6 +215,7 @@ static int make_config(const lddmm_grid* grid, const lddmm_params* p, int has_im
     }
   if (!build_levels(grid, c->L, c->lv)) return LDDMM_EINVAL;
   c->rows = multilevel ? trace_rows(p) : 1;
+  c->rk4 = (p->flags & LDDMM_FLAG_RK4) ? 1 : 0;
   c->ck = (p->flags & LDDMM_FLAG_RECOMPUTE_PHI) ? (p->checkpoint_every > 0 ? p->checkpoint_every
                                                                             : 1)
                                                 : 0;
@@ -352,6 +354,7 @@ static void forward_steps(Ctx& c, int li, const float* vA, const float* vB, cons
     a.partD = c.partD;
     a.partI = c.partI;
     a.st = c.st;
+    a.rk4 = k.rk4;
     ProfScope ps(LDDMM_PROF_FORWARD, n, s);
     launch_forward(a, s);
   }
@@ -455,7 +458,8 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
     a.partDet = c.partDet + (long long)(a.jb >= 0 ? a.jb : 0) * kPartMax;
     a.st = c.st;
     a.need_mode = need_mode;
-    a.staged = backward_staged(L.g);
+    a.rk4 = k.rk4;
+    a.staged = backward_staged(L.g) && !k.rk4;     // the staged kernel is first-order
     if (a.j < 0 && a.jb < 0) continue;
     {
       ProfScope ps(LDDMM_PROF_BACKWARD, n, s);
@@ -874,6 +878,7 @@ static void batch_offsets(BatchRef& br, int np, const int* tiles, PairTab* const
 extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const lddmm_params* prm,
                                       int32_t* status, void* stream) {
   if (!probs || !prm || n < 1 || n > kMaxBatch) return LDDMM_EINVAL;
+  if (prm->flags & LDDMM_FLAG_RK4) return LDDMM_EINVAL;     // batched kernels are first-order
   std::vector<Ctx> cs(n);
   for (int p = 0; p < n; ++p) {
     int rc = prepare(cs[p], &probs[p], prm, 1);
@@ -1043,6 +1048,7 @@ int lddmm_gradient(const lddmm_problem* p, const lddmm_params* prm, int32_t kind
                    double* out4, void* stream) {
   if (!grad || !out4) return LDDMM_EINVAL;
   if (kind != LDDMM_GRAD_V && kind != LDDMM_GRAD_L2) return LDDMM_EINVAL;
+  if (kind == LDDMM_GRAD_L2 && prm && (prm->flags & LDDMM_FLAG_RK4)) return LDDMM_EINVAL;
   Ctx c{};
   int rc = prepare(c, p, prm, 0);
   if (rc) return rc;

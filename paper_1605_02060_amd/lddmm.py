@@ -27,6 +27,7 @@ F32, I32 = 0, 1
 MAX_LEVELS = 4
 TRACE_COLS = 8
 FLAG_RECOMPUTE_PHI = 1
+FLAG_RK4 = 2
 
 
 class LddmmError(RuntimeError):
@@ -211,7 +212,30 @@ def workspace(shape, params: Params, spacing=1.0, device="cuda"):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10=None, phi01=None, trace=None):
+def _expect(t, shape, dtype, what):
+    """Shape and type check of a tensor handed to the library: the C ABI takes bare
+    pointers, so a wrongly sized buffer would be read or written out of range."""
+    if t is None:
+        return
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+        raise ValueError(f"{what}: expected {dtype} of shape {tuple(shape)}, got {t.dtype} "
+                         f"of shape {tuple(t.shape)}")
+
+
+def _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10=None, phi01=None, trace=None, params=None):
+    N = tuple(M0.shape)
+    if len(N) != 3:
+        raise ValueError("masks must be 3-D [Nz, Ny, Nx]")
+    for t, name in ((M0, "M0"), (M1, "M1"), (MI0, "MI0"), (MI1, "MI1")):
+        _expect(t, N, torch.float32, name)
+    for t, name in ((phi10, "phi10"), (phi01, "phi01")):
+        _expect(t, (3,) + N, torch.float32, name)
+    if params is not None:
+        P = lddmm_comp_grid(N, params, 0, spacing)
+        _expect(v, (params.T, 3) + P, torch.float32, "v")
+        _expect(trace, (lddmm_trace_rows(params), TRACE_COLS), torch.float64, "trace")
+    if ws.dtype != torch.uint8 or ws.dim() != 1:
+        raise ValueError("workspace: expected a 1-D uint8 tensor")
     pr = _Problem()
     pr.grid = _grid(M0.shape, spacing)
     pr.template_mask = _ptr(M0)
@@ -242,7 +266,7 @@ def lddmm_register(M0, M1, MI0=None, MI1=None, params: Params = None, spacing=1.
     trace = torch.full((rows, TRACE_COLS), float("nan"), dtype=torch.float64, device=dev)
     phi10 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
     phi01 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
-    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10, phi01, trace)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10, phi01, trace, params)
     code = load().lddmm_register(ctypes.byref(pr), 1, ctypes.byref(params.c()), _stream(stream))
     _check(code, "lddmm_register", ok=(OK, WFOLD, WGUARD, ENONFINITE))
     return {"v": v, "phi10": phi10, "phi01": phi01, "trace": trace, "status": code}
@@ -271,7 +295,7 @@ def lddmm_register_batched(pairs, params: Params = None, vs=None, wss=None, want
         trace = torch.full((rows, TRACE_COLS), float("nan"), dtype=torch.float64, device=dev)
         phi10 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
         phi01 = torch.empty((3,) + tuple(M0.shape), dtype=torch.float32, device=dev) if want_phi else None
-        arr[k] = _problem(M0, M1, MI0, MI1, v, h, ws, phi10, phi01, trace)
+        arr[k] = _problem(M0, M1, MI0, MI1, v, h, ws, phi10, phi01, trace, params)
         keep.append((M0, M1, MI0, MI1, ws))
         results.append({"v": v, "phi10": phi10, "phi01": phi01, "trace": trace})
     status = (ctypes.c_int32 * n)()
@@ -286,7 +310,7 @@ def lddmm_energy(M0, M1, MI0, MI1, v, params: Params, spacing=1.0, ws=None, stre
     """(E, R, D, image SSD) of v as a float64 device tensor of 4."""
     ws = ws if ws is not None else workspace(M0.shape, params, spacing, M0.device)
     out = torch.empty(4, dtype=torch.float64, device=M0.device)
-    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=params)
     _check(load().lddmm_energy(ctypes.byref(pr), ctypes.byref(params.c()), _ptr(out),
                                _stream(stream)), "lddmm_energy")
     return out
@@ -298,7 +322,7 @@ def lddmm_gradient(M0, M1, MI0, MI1, v, params: Params, kind=GRAD_V, spacing=1.0
     ws = ws if ws is not None else workspace(M0.shape, params, spacing, M0.device)
     out = torch.empty(4, dtype=torch.float64, device=M0.device)
     grad = torch.empty_like(v)
-    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=params)
     _check(load().lddmm_gradient(ctypes.byref(pr), ctypes.byref(params.c()), int(kind),
                                  _ptr(grad), _ptr(out), _stream(stream)), "lddmm_gradient")
     return grad, out
@@ -307,6 +331,9 @@ def lddmm_gradient(M0, M1, MI0, MI1, v, params: Params, kind=GRAD_V, spacing=1.0
 def lddmm_apply(u, src, spacing=1.0, interp=INTERP_LINEAR, stream=None):
     """dst(x) = src(x + u(x)/h): linear (float32) or nearest (float32 / int32 labels)."""
     dtype = I32 if src.dtype == torch.int32 else F32
+    if src.dim() != 3 or src.dtype not in (torch.int32, torch.float32):
+        raise ValueError("src: expected a 3-D float32 or int32 tensor")
+    _expect(u, (3,) + tuple(src.shape), torch.float32, "u")
     dst = torch.empty_like(src)
     g = _grid(src.shape, spacing)
     _check(load().lddmm_apply(ctypes.byref(g), _ptr(u), _ptr(src), int(interp), dtype, _ptr(dst),
@@ -316,6 +343,8 @@ def lddmm_apply(u, src, spacing=1.0, interp=INTERP_LINEAR, stream=None):
 
 def lddmm_smooth(b, spacing, alpha, gamma, stream=None):
     """K b on the computational grid of b ([3, Pz, Py, Px], each axis 7-smooth)."""
+    if b.dim() != 4 or b.shape[0] != 3 or b.dtype != torch.float32:
+        raise ValueError("b: expected float32 of shape [3, Pz, Py, Px]")
     Pz, Py, Px = b.shape[1:]
     P = (ctypes.c_int32 * 3)(Px, Py, Pz)
     nbytes = load().lddmm_smooth_workspace_size(P)

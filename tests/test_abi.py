@@ -73,3 +73,21 @@ def test_host_side_queries_without_gpu():
     bad = L.Params(T=0)
     assert L.lddmm_workspace_size((32, 32, 32), bad) == 0
     assert L.strerror(L.EINVAL) == "invalid argument"
+
+
+def test_binding_rejects_wrongly_sized_buffers():
+    # the C ABI takes bare pointers: the binding checks every shape before a call
+    import torch
+    N = (13, 17, 19)
+    M = torch.zeros(N)
+    prm = L.Params(T=3, iters=(1,))
+    P = L.lddmm_comp_grid(N, prm, 0, 1.0)
+    assert P != N
+    with pytest.raises(ValueError, match="v:"):
+        L.lddmm_register(M, M, params=prm, v=torch.zeros((3, 3) + N))
+    with pytest.raises(ValueError, match="MI0"):
+        L.lddmm_register(M, M, torch.zeros(N[::-1]), None, params=prm)
+    with pytest.raises(ValueError, match="M1"):
+        L.lddmm_register(M, torch.zeros(N, dtype=torch.float64), params=prm)
+    with pytest.raises(ValueError, match="u:"):
+        L.lddmm_apply(torch.zeros((3, 13, 17, 18)), M)
