@@ -193,6 +193,51 @@ int lddmm_smooth(const int32_t P[3], double spacing, double alpha, double gamma,
 int lddmm_make_mask(const lddmm_grid *grid, const float *image, float tau, float *mask,
                     float *masked_image, void *stream);
 
+/* Mask application (Methods, Preprocessing): out = image where mask > 0, else 0,
+ * on N (device, float32; out may alias image).  Async; LDDMM_EINVAL for a null
+ * pointer or an axis outside [1, LDDMM_MAX_DIM]. */
+int lddmm_mask_image(const lddmm_grid *grid, const float *image, const float *mask, float *out,
+                     void *stream);
+
+/*
+ * Histogram matching of the Image-LDDMM preprocessing (Methods, Preprocessing):
+ * the masked source (template) image is mapped so that its in-mask intensity
+ * distribution matches that of the masked reference (target) image.
+ *  - Histograms: n_bins equal-width bins over [lo, hi], the in-mask (mask > 0)
+ *    minimum and maximum of each image; only in-mask voxels are counted.  The
+ *    bin of x is floor((x - lo) * (n_bins / (hi - lo))) evaluated in float32,
+ *    clamped to the last bin (bin 0 for a constant image).
+ *  - Quantiles: the p-quantile of a histogram is where its piecewise-uniform
+ *    cumulative distribution (each bin's count spread evenly over the bin)
+ *    reaches p.  The match points are lo, the quantiles at p = k/(n_points+1)
+ *    for k = 1..n_points, and hi, for both images (FP64).
+ *  - Map: between neighbouring source points, the straight line through the
+ *    matched pairs (FP64, rounded once to float32); a value at or above the
+ *    last source point maps to the reference maximum.
+ * out[i] = mapped src[i] where src_mask[i] > 0, else 0; all zero if either mask
+ * is empty.  The paper uses n_bins = 32 and n_points = 8.
+ * src, src_mask, out: [src_grid N]; ref, ref_mask: [ref_grid N]; device float32;
+ * the two grids may differ; out must not alias an input.
+ * points (device, may be NULL): out, [2][n_points + 2] doubles, source points
+ * then reference points.  counts (device, may be NULL): out, [2][n_bins] int64
+ * bin counts, source then reference.
+ * workspace: device scratch of lddmm_histogram_match_workspace_size bytes
+ * (caller-owned, no state kept between calls).
+ * Async on `stream`.  Returns LDDMM_OK, LDDMM_EINVAL (null pointer, an axis
+ * outside [1, LDDMM_MAX_DIM], n_bins outside [1, LDDMM_HIST_MAX_BINS], n_points
+ * outside [0, LDDMM_HIST_MAX_POINTS], workspace too small; nothing launched) or
+ * LDDMM_EHIP.
+ */
+#define LDDMM_HIST_MAX_BINS   1024
+#define LDDMM_HIST_MAX_POINTS 62
+size_t lddmm_histogram_match_workspace_size(const lddmm_grid *src_grid,
+                                            const lddmm_grid *ref_grid, int32_t n_bins);
+int lddmm_histogram_match(const lddmm_grid *src_grid, const float *src, const float *src_mask,
+                          const lddmm_grid *ref_grid, const float *ref, const float *ref_mask,
+                          int32_t n_bins, int32_t n_points, float *out, double *points,
+                          int64_t *counts, void *workspace, size_t workspace_bytes,
+                          void *stream);
+
 /*
  * Kernel-class timing with HIP events recorded on the launch stream around each
  * launch of the selected classes (bit k of class_mask = class k below) whose

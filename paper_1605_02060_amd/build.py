@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm.so")
 
-SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip", "cnn.hip"]
+SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip", "cnn.hip", "hist.hip"]
 ARCH = "gfx950"
 
 
@@ -36,11 +36,15 @@ def common_flags():
 # grid-stride and LDS-staged): multiply-add fusion only within one source
 # expression, so both give the same bits.
 CONTRACT_ON = {"flow.hip"}
+# Sources whose FP64 arithmetic restates a definition operation by operation
+# (histogram quantiles and the intensity map): no multiply-add fusion at all.
+CONTRACT_OFF = {"hist.hip"}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    extra = ["-ffp-contract=on"] if src in CONTRACT_ON else []
+    extra = (["-ffp-contract=on"] if src in CONTRACT_ON else
+             ["-ffp-contract=off"] if src in CONTRACT_OFF else [])
     cmd = [hipcc(), *common_flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -95,6 +95,13 @@ def load():
     lib.lddmm_smooth.restype = ctypes.c_int
     lib.lddmm_make_mask.argtypes = [P(_Grid), vp, ctypes.c_float, vp, vp, vp]
     lib.lddmm_make_mask.restype = ctypes.c_int
+    lib.lddmm_mask_image.argtypes = [P(_Grid), vp, vp, vp, vp]
+    lib.lddmm_mask_image.restype = ctypes.c_int
+    lib.lddmm_histogram_match_workspace_size.argtypes = [P(_Grid), P(_Grid), i32]
+    lib.lddmm_histogram_match_workspace_size.restype = sz
+    lib.lddmm_histogram_match.argtypes = [P(_Grid), vp, vp, P(_Grid), vp, vp, i32, i32, vp, vp,
+                                          vp, vp, sz, vp]
+    lib.lddmm_histogram_match.restype = ctypes.c_int
     lib.lddmm_profile_begin.argtypes = [ctypes.c_uint32, ctypes.c_int64]
     lib.lddmm_profile_begin.restype = ctypes.c_int
     lib.lddmm_profile_end.argtypes = [vp, vp, vp]
@@ -110,7 +117,9 @@ def load():
 EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddmm_register",
             "lddmm_register_batched",
             "lddmm_energy", "lddmm_gradient", "lddmm_apply", "lddmm_smooth_workspace_size",
-            "lddmm_smooth", "lddmm_make_mask", "lddmm_profile_begin", "lddmm_profile_end",
+            "lddmm_smooth", "lddmm_make_mask", "lddmm_mask_image",
+            "lddmm_histogram_match_workspace_size", "lddmm_histogram_match",
+            "lddmm_profile_begin", "lddmm_profile_end",
             "lddmm_set_tunable", "lddmm_strerror"]
 
 TUNE_SWEEP_BLOCKS = 0
@@ -365,6 +374,58 @@ def lddmm_make_mask(image, tau, stream=None):
     _check(load().lddmm_make_mask(ctypes.byref(g), _ptr(image), float(tau), _ptr(m), _ptr(mi),
                                   _stream(stream)), "lddmm_make_mask")
     return m, mi
+
+
+def lddmm_mask_image(image, mask, stream=None):
+    """image where mask > 0, else 0 (Methods, Preprocessing)."""
+    _expect(mask, tuple(image.shape), torch.float32, "mask")
+    _expect(image, tuple(mask.shape), torch.float32, "image")
+    out = torch.empty_like(image)
+    g = _grid(image.shape, 1.0)
+    _check(load().lddmm_mask_image(ctypes.byref(g), _ptr(image), _ptr(mask), _ptr(out),
+                                   _stream(stream)), "lddmm_mask_image")
+    return out
+
+
+HIST_MAX_BINS = 1024
+HIST_MAX_POINTS = 62
+
+
+def lddmm_histogram_match_workspace_size(src_shape, ref_shape, n_bins=32) -> int:
+    return int(load().lddmm_histogram_match_workspace_size(
+        ctypes.byref(_grid(src_shape, 1.0)), ctypes.byref(_grid(ref_shape, 1.0)), int(n_bins)))
+
+
+def lddmm_histogram_match(src, src_mask, ref, ref_mask, n_bins=32, n_points=8, ws=None,
+                          want_points=True, want_counts=True, stream=None):
+    """Masked src with its in-mask intensities histogram-matched to the masked ref
+    (Methods, Preprocessing).  Returns (out [src N], points [2, n_points+2] float64
+    or None, counts [2, n_bins] int64 or None), all device tensors."""
+    if src.dim() != 3 or ref.dim() != 3:
+        raise ValueError("src and ref must be 3-D [Nz, Ny, Nx]")
+    _expect(src, tuple(src.shape), torch.float32, "src")
+    _expect(src_mask, tuple(src.shape), torch.float32, "src_mask")
+    _expect(ref, tuple(ref.shape), torch.float32, "ref")
+    _expect(ref_mask, tuple(ref.shape), torch.float32, "ref_mask")
+    dev = src.device
+    if ws is None:
+        nbytes = lddmm_histogram_match_workspace_size(src.shape, ref.shape, n_bins)
+        if nbytes == 0:
+            raise LddmmError(EINVAL, "lddmm_histogram_match_workspace_size")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if ws.dtype != torch.uint8 or ws.dim() != 1:
+        raise ValueError("workspace: expected a 1-D uint8 tensor")
+    out = torch.empty_like(src)
+    points = (torch.empty((2, int(n_points) + 2), dtype=torch.float64, device=dev)
+              if want_points and 0 <= n_points <= HIST_MAX_POINTS else None)
+    counts = (torch.empty((2, int(n_bins)), dtype=torch.int64, device=dev)
+              if want_counts and 1 <= n_bins <= HIST_MAX_BINS else None)
+    gs, gr = _grid(src.shape, 1.0), _grid(ref.shape, 1.0)
+    _check(load().lddmm_histogram_match(
+        ctypes.byref(gs), _ptr(src), _ptr(src_mask), ctypes.byref(gr), _ptr(ref), _ptr(ref_mask),
+        int(n_bins), int(n_points), _ptr(out), _ptr(points), _ptr(counts), _ptr(ws), ws.numel(),
+        _stream(stream)), "lddmm_histogram_match")
+    return out, points, counts
 
 
 def lddmm_profile_begin(class_mask=0xFF, min_voxels=0):
