@@ -109,6 +109,13 @@ def cpu_baseline(pair, budget_s=20.0):
                       "single-threaded elementwise and numpy.fft"}
 
 
+def _short_name(name):
+    """Kernel name without namespaces and argument list."""
+    import re
+    name = name.replace("(anonymous namespace)::", "").replace("lddmm::", "")
+    return re.sub(r"\(.*", "", name)
+
+
 def _kernel_rows(db):
     """Per-dispatch rows (name, grid threads, duration ns, counter, value) of a rocprofv3 DB."""
     import re
@@ -118,13 +125,13 @@ def _kernel_rows(db):
     try:
         q = "select kernel_name, grid_size, duration, counter_name, value from counters_collection"
         for name, grid, dur, cn, val in c.execute(q):
-            out.append((re.sub(r"\(.*", "", name).replace("lddmm::", ""), grid, dur, cn, val))
+            out.append((_short_name(name), grid, dur, cn, val))
     except sqlite3.Error:
         pass
     if not out:
         q = "select name, grid_x*grid_y*grid_z, duration from kernels"
         for name, grid, dur in c.execute(q):
-            out.append((re.sub(r"\(.*", "", name).replace("lddmm::", ""), grid, dur, None, None))
+            out.append((_short_name(name), grid, dur, None, None))
     return out
 
 
@@ -359,6 +366,119 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+HIST_CALLS = 100            # histogram matches per step of the histmatch workload
+HIST_BINS, HIST_POINTS = 32, 8
+# Algorithmic bytes per voxel of each histogram-matching pass (FP32 image + mask):
+#  range (in-mask min / max): read I, M of both images     8 per voxel of either image
+#  count (bins + point table): read I, M of both images    8 per voxel of either image
+#  apply (map): read I0, M0, write the matched image      12 per template voxel
+HIST_ALG_BYTES = {"hist_range": 8.0, "hist_count": 8.0, "hist_apply": 12.0}
+
+
+def hist_cpu_baseline(pair, budget_s=15.0):
+    """The oracle's histogram matching of the same pair, repeated for about budget_s."""
+    from oracle import histmatch as H
+    t0 = time.perf_counter()
+    calls = 0
+    while True:
+        H.histogram_match(pair.I0, pair.M0, pair.I1, pair.M1, HIST_BINS, HIST_POINTS)
+        calls += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": calls * (pair.M0.size + pair.M1.size) / dt, "unit": "voxel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{calls} full histogram matches of the same 264x160x228 pair in {dt:.1f} s; "
+                      "NumPy (float32 bins, FP64 table and map), single-threaded"}
+
+
+def bench_histmatch(args):
+    """Image-LDDMM preprocessing at the atlas size (Methods, Preprocessing): the
+    atlas-like template image, masked, histogram-matched (32 bins, 8 quantile
+    points) to the masked sparse target image, both 264 x 160 x 228."""
+    import torch
+    from paper_1605_02060_amd import lddmm as L
+    from paper_1605_02060_amd import synth
+
+    L.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    log("generating atlas-like pair ...")
+    pair = synth.config_pair("atlas")
+    tt = lambda a: torch.as_tensor(a, device="cuda")
+    I0, M0, I1, M1 = tt(pair.I0.astype(np.float32)), tt(pair.M0), tt(pair.I1.astype(np.float32)), \
+        tt(pair.M1)
+    ns, nr = pair.M0.size, pair.M1.size
+    ws = torch.empty(L.lddmm_histogram_match_workspace_size(pair.shape, pair.shape, HIST_BINS),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        for _ in range(HIST_CALLS):
+            res = L.lddmm_histogram_match(I0, M0, I1, M1, HIST_BINS, HIST_POINTS, ws=ws,
+                                          want_points=True, want_counts=False)
+        return res
+
+    for w in range(max(args.warmup, 1)):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w} done")
+    classes = ("hist_range", "hist_count", "hist_apply")
+    L.lddmm_profile_begin(sum(1 << L.PROF_CLASSES.index(c) for c in classes), 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, pts, _ = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = L.lddmm_profile_end()
+    calls = HIST_CALLS * args.steps
+    value = calls * (ns + nr) / elapsed
+    per = {}
+    for c in classes:
+        avg_ms = prof[c]["ms"] / max(prof[c]["launches"], 1)
+        vox = prof[c]["voxels"] / max(prof[c]["launches"], 1)
+        per[c] = {"avg_us": 1e3 * avg_ms, "voxels": vox,
+                  "GBs": HIST_ALG_BYTES[c] * vox / (avg_ms * 1e-3) / 1e9}
+    dominant = max(classes, key=lambda c: per[c]["avg_us"])
+    achieved = per[dominant]["GBs"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = hist_cpu_baseline(pair)
+    pts = pts.cpu().numpy()
+    res = {
+        "metric": "histogram-matched voxels/s (Image-LDDMM preprocessing)",
+        "value": value,
+        "unit": "voxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 bins, f64 table and map",
+        "data": "synthetic (seeded atlas-like template, sparse Poisson-labelled warped target)",
+        "config": {"workload": f"histogram matching of the masked 264x160x228 atlas-like template "
+                               f"image to the masked sparse target image, {HIST_BINS} bins, "
+                               f"{HIST_POINTS} quantile points; {HIST_CALLS} matches per step",
+                   "grid": [264, 160, 228], "bins": HIST_BINS, "points": HIST_POINTS,
+                   "calls_per_step": HIST_CALLS},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": {"hist_range": "k_hist_range_part + k_hist_range_final",
+                                "hist_count": "k_hist_count + k_hist_sum + k_hist_table",
+                                "hist_apply": "k_hist_apply"}[dominant],
+                     "alg_bytes_per_voxel": HIST_ALG_BYTES[dominant],
+                     "avg_launch_ms": per[dominant]["avg_us"] / 1e3,
+                     "voxels_per_launch": per[dominant]["voxels"]},
+        "passes": per,
+        "call_us": 1e6 * elapsed / calls,
+        "points": {"template": list(pts[0]), "target": list(pts[1])},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,9 +486,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-out", default=None)
-    ap.add_argument("--workload", choices=("atlas", "batched"), default="atlas",
+    ap.add_argument("--workload", choices=("atlas", "batched", "histmatch"), default="atlas",
                     help="atlas (default): the single-pair atlas registration; batched: 16 "
-                         "uneven pairs in one grouped launch sequence vs 16 sequential runs")
+                         "uneven pairs in one grouped launch sequence vs 16 sequential runs; "
+                         "histmatch: the Image-LDDMM histogram matching of the atlas pair")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("DB", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 database and exit")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "OUT"),
@@ -386,6 +507,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "histmatch":
+        bench_histmatch(args)
         return
 
     import torch

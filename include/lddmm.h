@@ -256,7 +256,10 @@ int lddmm_histogram_match(const lddmm_grid *src_grid, const float *src, const fl
 #define LDDMM_PROF_FFT_YINV  5   /* y inverse pass */
 #define LDDMM_PROF_FFT_XINV  6   /* x inverse pass + velocity update */
 #define LDDMM_PROF_OTHER     7   /* retry, guard decision, pyramid, setup */
-#define LDDMM_PROF_CLASSES   8
+#define LDDMM_PROF_HIST_RANGE  8 /* histogram matching: in-mask range (two launches) */
+#define LDDMM_PROF_HIST_COUNT  9 /* histogram matching: bin counts, totals, point table (three launches) */
+#define LDDMM_PROF_HIST_APPLY 10 /* histogram matching: intensity map */
+#define LDDMM_PROF_CLASSES  11
 int lddmm_profile_begin(uint32_t class_mask, int64_t min_voxels);
 int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 

@@ -10,8 +10,10 @@
 //      of a wavefront only contend with themselves), written out as per-block
 //      partial counts: no global atomics and nothing to clear beforehand, and
 //      the integer sums do not depend on the order they are added in;
-//   4. one block sums the partial counts, walks the cumulative histogram once
-//      per image for the quantile points and writes the FP64 point table;
+//   4. one block per (bin, image) sums that bin's partial counts (stored
+//      bin-major, so each sum reads contiguous memory); then one block walks
+//      the cumulative histogram once per image for the quantile points and
+//      writes the FP64 point table;
 //   5. the map itself, one FP64 polyline evaluation per in-mask voxel.
 // The bin decision is taken in float32 (the stored precision); the table and
 // the map are FP64 with no multiply-add fusion (this file is compiled with
@@ -51,7 +53,7 @@ struct HistRange {
 };
 
 struct HistLayout {
-  size_t plo, phi, pn, range, pcount, table, total;
+  size_t plo, phi, pn, range, pcount, totals, table, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -72,6 +74,7 @@ HistLayout hist_layout(int nblk, int nbins) {
   L.pn = o;     o = align256(o + sizeof(unsigned) * 2 * nblk);
   L.range = o;  o = align256(o + sizeof(HistRange) * 2);
   L.pcount = o; o = align256(o + sizeof(unsigned) * 2 * (size_t)nblk * nbins);
+  L.totals = o; o = align256(o + sizeof(unsigned long long) * 2 * nbins);
   L.table = o;  o = align256(o + sizeof(HistTable));
   L.total = o;
   return L;
@@ -161,14 +164,21 @@ __global__ __launch_bounds__(kBlock) void k_hist_range_final(const float* __rest
     hi = fmaxf(hi, phi[img * nblk + k]);
     n += pn[img * nblk + k];
   }
-  __shared__ float slo[kBlock], shi[kBlock];
-  __shared__ unsigned long long sn[kBlock];
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
-  sn[threadIdx.x] = n;
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o));
+    hi = fmaxf(hi, __shfl_xor(hi, o));
+    n += __shfl_xor(n, o);
+  }
+  __shared__ float slo[kWaves], shi[kWaves];
+  __shared__ unsigned long long sn[kWaves];
+  if ((threadIdx.x & 63) == 0) {
+    slo[threadIdx.x >> 6] = lo;
+    shi[threadIdx.x >> 6] = hi;
+    sn[threadIdx.x >> 6] = n;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 1; k < kBlock; ++k) {
+    for (int k = 1; k < kWaves; ++k) {
       lo = fminf(lo, slo[k]);
       hi = fmaxf(hi, shi[k]);
       n += sn[k];
@@ -219,11 +229,11 @@ __global__ __launch_bounds__(kBlock) void k_hist_count(HistImage a, HistImage b,
   for (long long i = done + t0; i < im.n; i += stride)
     if (im.M[i] > 0.f) bin_add(h, im.I[i], R.lo, R.scale, nbins);
   __syncthreads();
-  unsigned* out = pcount + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nbins;
+  // bin-major partials: pcount[img][bin][block]
   for (int k = threadIdx.x; k < nbins; k += kBlock) {
     unsigned c = 0;
     for (int w = 0; w < kWaves; ++w) c += hl[w * nbins + k];
-    out[k] = c;
+    pcount[((size_t)blockIdx.y * nbins + k) * gridDim.x + blockIdx.x] = c;
   }
 }
 
@@ -254,28 +264,37 @@ __device__ void quantile_points(const unsigned long long* cnt, int nbins, const 
   pts[npts + 1] = hi;
 }
 
-// Pass 4: one block; totals per bin (integer sums in LDS: order-free), quantile
-// points, slopes.
-__global__ __launch_bounds__(kBlock) void k_hist_table(const unsigned* __restrict__ pcount,
-                                                       int nblk, int nbins, int npts,
+// Pass 4a: one block per (bin, image): the bin's total over the partial blocks.
+__global__ __launch_bounds__(kBlock) void k_hist_sum(const unsigned* __restrict__ pcount, int nblk,
+                                                     unsigned long long* __restrict__ totals) {
+  const int row = blockIdx.y * gridDim.x + blockIdx.x;          // img * nbins + bin
+  const unsigned* p = pcount + (size_t)row * nblk;
+  unsigned long long c = 0;
+  for (int j = threadIdx.x; j < nblk; j += kBlock) c += p[j];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  __shared__ unsigned long long sc[kWaves];
+  if ((threadIdx.x & 63) == 0) sc[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWaves; ++w) c += sc[w];
+    totals[row] = c;
+  }
+}
+
+// Pass 4b: one block; quantile points and slopes from the bin totals.
+__global__ __launch_bounds__(kBlock) void k_hist_table(const unsigned long long* __restrict__ totals,
+                                                       int nbins, int npts,
                                                        const HistRange* __restrict__ range,
                                                        HistTable* __restrict__ table,
                                                        double* __restrict__ points,
                                                        long long* __restrict__ counts) {
   extern __shared__ unsigned long long cs[];           // [2][nbins]
   __shared__ double pts[2][kTablePts];
-  for (int k = threadIdx.x; k < 2 * nbins; k += kBlock) cs[k] = 0ull;
-  __syncthreads();
-  const long long per_img = (long long)nblk * nbins;
-  for (long long f = threadIdx.x; f < 2 * per_img; f += kBlock) {
-    const int img = f >= per_img ? 1 : 0;
-    const int bin = (int)((f - img * per_img) % nbins);
-    const unsigned c = pcount[f];
-    if (c) atomicAdd(&cs[img * nbins + bin], (unsigned long long)c);
+  for (int k = threadIdx.x; k < 2 * nbins; k += kBlock) {
+    cs[k] = totals[k];
+    if (counts) counts[k] = (long long)totals[k];
   }
   __syncthreads();
-  if (counts)
-    for (int k = threadIdx.x; k < 2 * nbins; k += kBlock) counts[k] = (long long)cs[k];
   if (threadIdx.x < 2) {
     const HistRange R = range[threadIdx.x];
     if (R.n > 0) quantile_points(cs + threadIdx.x * nbins, nbins, R, npts, pts[threadIdx.x]);
@@ -406,19 +425,30 @@ int lddmm_histogram_match(const lddmm_grid* src_grid, const float* src, const fl
   unsigned* pn = reinterpret_cast<unsigned*>(ws + L.pn);
   HistRange* range = reinterpret_cast<HistRange*>(ws + L.range);
   unsigned* pcount = reinterpret_cast<unsigned*>(ws + L.pcount);
+  unsigned long long* totals = reinterpret_cast<unsigned long long*>(ws + L.totals);
   HistTable* table = reinterpret_cast<HistTable*>(ws + L.table);
   const HistImage a{src, src_mask, ns}, b{ref, ref_mask, nr};
   hipStream_t s = (hipStream_t)stream;
   hipGetLastError();
-  hipLaunchKernelGGL(k_hist_range_part, dim3(nblk, 2), dim3(kBlock), 0, s, a, b, plo, phi, pn);
-  hipLaunchKernelGGL(k_hist_range_final, dim3(2), dim3(kBlock), 0, s, plo, phi, pn, nblk,
-                     (int)n_bins, range);
-  hipLaunchKernelGGL(k_hist_count, dim3(nblk, 2), dim3(kBlock),
-                     sizeof(unsigned) * kWaves * n_bins, s, a, b, (int)n_bins, range, pcount);
-  hipLaunchKernelGGL(k_hist_table, dim3(1), dim3(kBlock), sizeof(unsigned long long) * 2 * n_bins,
-                     s, pcount, nblk, (int)n_bins, (int)n_points, range, table, points,
-                     reinterpret_cast<long long*>(counts));
-  hipLaunchKernelGGL(k_hist_apply, dim3(stream_blocks(ns)), dim3(kBlock), 0, s, a, table, out);
+  {
+    ProfScope ps(LDDMM_PROF_HIST_RANGE, ns + nr, s);
+    hipLaunchKernelGGL(k_hist_range_part, dim3(nblk, 2), dim3(kBlock), 0, s, a, b, plo, phi, pn);
+    hipLaunchKernelGGL(k_hist_range_final, dim3(2), dim3(kBlock), 0, s, plo, phi, pn, nblk,
+                       (int)n_bins, range);
+  }
+  {
+    ProfScope ps(LDDMM_PROF_HIST_COUNT, ns + nr, s);
+    hipLaunchKernelGGL(k_hist_count, dim3(nblk, 2), dim3(kBlock),
+                       sizeof(unsigned) * kWaves * n_bins, s, a, b, (int)n_bins, range, pcount);
+    hipLaunchKernelGGL(k_hist_sum, dim3(n_bins, 2), dim3(kBlock), 0, s, pcount, nblk, totals);
+    hipLaunchKernelGGL(k_hist_table, dim3(1), dim3(kBlock),
+                       sizeof(unsigned long long) * 2 * n_bins, s, totals, (int)n_bins,
+                       (int)n_points, range, table, points, reinterpret_cast<long long*>(counts));
+  }
+  {
+    ProfScope ps(LDDMM_PROF_HIST_APPLY, ns, s);
+    hipLaunchKernelGGL(k_hist_apply, dim3(stream_blocks(ns)), dim3(kBlock), 0, s, a, table, out);
+  }
   return launch_status();
 }
 

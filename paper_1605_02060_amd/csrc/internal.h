@@ -35,6 +35,20 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
   return (__umulhi(n, f.m) + n) >> f.s;
 }
 
+// Kernel-class timing (lddmm_profile_begin / lddmm_profile_end): HIP events
+// recorded on the launch stream around each launch of an enabled class whose
+// grid has at least the selected number of voxels.
+void prof_open(int cls, long long vox, hipStream_t s, hipEvent_t* a);
+void prof_close(int cls, long long vox, hipStream_t s, hipEvent_t a);
+struct ProfScope {
+  int cls;
+  long long vox;
+  hipStream_t s;
+  hipEvent_t a;
+  ProfScope(int c, long long n, hipStream_t st) : cls(c), vox(n), s(st) { prof_open(c, n, st, &a); }
+  ~ProfScope() { prof_close(cls, vox, s, a); }
+};
+
 // Computational grid of one pyramid level.
 struct Geom {
   int nx, ny, nz;   // P (each axis 7-smooth)

@@ -34,25 +34,21 @@ static hipEvent_t prof_event() {
   return g_prof_pool[g_prof_used++];
 }
 
-struct ProfScope {
-  int cls;
-  long long vox;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  ProfScope(int c, long long n, hipStream_t st) : cls(c), vox(n), s(st) {
-    if ((g_prof_mask & (1u << cls)) && vox >= g_prof_min_vox) {
-      a = prof_event();
-      if (a) hipEventRecord(a, s);
-    }
+void prof_open(int cls, long long vox, hipStream_t s, hipEvent_t* a) {
+  *a = nullptr;
+  if ((g_prof_mask & (1u << cls)) && vox >= g_prof_min_vox) {
+    *a = prof_event();
+    if (*a) hipEventRecord(*a, s);
   }
-  ~ProfScope() {
-    if (!a) return;
-    hipEvent_t b = prof_event();
-    if (!b) return;
-    hipEventRecord(b, s);
-    g_prof_rec.push_back({cls, a, b, vox});
-  }
-};
+}
+
+void prof_close(int cls, long long vox, hipStream_t s, hipEvent_t a) {
+  if (!a) return;
+  hipEvent_t b = prof_event();
+  if (!b) return;
+  hipEventRecord(b, s);
+  g_prof_rec.push_back({cls, a, b, vox});
+}
 
 static bool is_7smooth(int n) {
   for (int p : {2, 3, 5, 7})

@@ -129,7 +129,7 @@ TUNE_FFT_ZCOLS = 3
 TUNE_STAGED_MIN_BLOCKS = 4
 
 PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
-                "other"]
+                "other", "hist_range", "hist_count", "hist_apply"]
 
 
 def strerror(code):
@@ -428,7 +428,7 @@ def lddmm_histogram_match(src, src_mask, ref, ref_mask, n_bins=32, n_points=8, w
     return out, points, counts
 
 
-def lddmm_profile_begin(class_mask=0xFF, min_voxels=0):
+def lddmm_profile_begin(class_mask=0x7FF, min_voxels=0):
     """Record HIP events around every launch of the selected kernel classes
     whose grid has at least min_voxels voxels."""
     _check(load().lddmm_profile_begin(int(class_mask), int(min_voxels)), "lddmm_profile_begin")

@@ -91,3 +91,12 @@ def test_binding_rejects_wrongly_sized_buffers():
         L.lddmm_register(M, torch.zeros(N, dtype=torch.float64), params=prm)
     with pytest.raises(ValueError, match="u:"):
         L.lddmm_apply(torch.zeros((3, 13, 17, 18)), M)
+
+
+def test_profile_classes_match_header():
+    src = open(os.path.join(ROOT, "include", "lddmm.h")).read()
+    n = int(re.search(r"#define LDDMM_PROF_CLASSES\s+(\d+)", src).group(1))
+    assert len(L.PROF_CLASSES) == n
+    for k, name in enumerate(("FORWARD", "BACKWARD", "FFT_X", "FFT_Y", "FFT_ZK", "FFT_YINV",
+                              "FFT_XINV", "OTHER", "HIST_RANGE", "HIST_COUNT", "HIST_APPLY")):
+        assert int(re.search(rf"#define LDDMM_PROF_{name}\s+(\d+)", src).group(1)) == k
