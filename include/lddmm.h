@@ -228,6 +228,74 @@ int lddmm_mask_image(const lddmm_grid *grid, const float *image, const float *ma
  * outside [0, LDDMM_HIST_MAX_POINTS], workspace too small; nothing launched) or
  * LDDMM_EHIP.
  */
+/*
+ * Rigid and affine pre-alignment (Methods, Registration): gradient descent on
+ * the mean squared error between the template image, sampled through an affine
+ * sampling map S, and the target image.
+ *  - S maps target positions to template positions, x = S(y) = B y + c, in
+ *    physical coordinates (voxel (i, j, k) of a grid with spacing h sits at
+ *    h (i, j, k)).  S = R^-1 in the rigid stage and R^-1 A^-1 in the affine
+ *    stage, so the template resampled through S is I0 o R^-1 (A^-1).
+ *  - MSE(S) = (1/n1) sum over target voxels y of (I0(S(y)) - I1(y))^2, with I0
+ *    trilinear in index coordinates S(y)/h0 and zero outside.  Its gradient is
+ *    the exact derivative of that interpolant: G_B = (2/n1) sum r g (y - y_c)^T
+ *    and G_c' = (2/n1) sum r g, with y_c the target centre and c' = B y_c + c.
+ *  - A step from the current iterate uses eps for c' and eps / rho^2 for the
+ *    linear part (rho^2: mean squared distance of the target voxels from y_c).
+ *    Rigid: B <- B exp(-eps/rho^2 [w]_x), w_k = <G_B, B [e_k]_x> (B stays a
+ *    rotation).  Affine: B <- B - eps/rho^2 G_B.
+ *  - Guard: a candidate whose MSE exceeds the current iterate's is rejected
+ *    and eps halved; more than max_halvings consecutive rejections stop the
+ *    descent.
+ */
+#define LDDMM_ALIGN_RIGID  0
+#define LDDMM_ALIGN_AFFINE 1
+#define LDDMM_ALIGN_TRACE_COLS 28   /* MSE, step, accepted, halvings, S[12], G_B[9], G_c'[3] */
+typedef struct {
+  int32_t mode;             /* LDDMM_ALIGN_RIGID or LDDMM_ALIGN_AFFINE */
+  int32_t iters;            /* descent slots after the starting evaluation */
+  double step;              /* eps: translation step (squared length per unit MSE gradient) */
+  int32_t max_halvings;     /* consecutive rejections before the descent stops */
+} lddmm_align_params;
+
+/* Bytes of device workspace lddmm_align needs for a target grid (0 if invalid). */
+size_t lddmm_align_workspace_size(const lddmm_grid *target_grid);
+
+/*
+ * Run the descent.  template_image [template N], target_image [target N]: device
+ * float32 (the grids may differ; each grid's spacing is its voxel size).
+ * affine: device, 12 doubles, row-major [B | c]: in = starting map (the identity
+ * with the grid centres lined up, or the rigid result for the affine stage),
+ * out = the final iterate.  trace (device, may be NULL): rows 0..iters of
+ * LDDMM_ALIGN_TRACE_COLS doubles; row 0 is the start, row s the candidate of
+ * slot s (its MSE, the step it used, 1 if accepted, the consecutive
+ * rejections), then the current iterate after the slot and its gradient; rows
+ * after a stop are not written.  workspace: lddmm_align_workspace_size bytes,
+ * caller-owned.  Async: 2 (iters + 1) + 2 launches, no host synchronisation.
+ * Returns LDDMM_OK, LDDMM_EINVAL (null pointer, an axis outside [1,
+ * LDDMM_MAX_DIM], spacing not positive, bad mode, iters or max_halvings < 0,
+ * step not positive, workspace too small; nothing launched) or LDDMM_EHIP.
+ */
+int lddmm_align(const lddmm_grid *template_grid, const float *template_image,
+                const lddmm_grid *target_grid, const float *target_image,
+                const lddmm_align_params *params, double *affine, double *trace,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Resample through an affine map composed with a displacement (Methods,
+ * Registration: phi^-1 = R^-1 A^-1 phi_10):
+ * dst(y) = src(S(y + u(y))) on dst_grid, S = affine (device, 12 doubles [B | c]),
+ * u = displacement in physical units on dst_grid ([3][N], device; NULL: none),
+ * src on src_grid.  LINEAR: trilinear, zero outside (LDDMM_F32).  NEAREST:
+ * src at floor(x/h + 1/2), zero outside (LDDMM_F32 or LDDMM_I32 labels).
+ * With u = phi_10 - id from lddmm_register this is the label transfer
+ * L0 o phi^-1; with u = NULL it resamples the template onto the target grid
+ * (J0 = I0 o R^-1 A^-1).  Async; LDDMM_EINVAL for invalid arguments.
+ */
+int lddmm_apply_affine(const lddmm_grid *dst_grid, const float *u, const double *affine,
+                       const lddmm_grid *src_grid, const void *src, int32_t interp,
+                       int32_t dtype, void *dst, void *stream);
+
 #define LDDMM_HIST_MAX_BINS   1024
 #define LDDMM_HIST_MAX_POINTS 62
 size_t lddmm_histogram_match_workspace_size(const lddmm_grid *src_grid,
@@ -259,7 +327,8 @@ int lddmm_histogram_match(const lddmm_grid *src_grid, const float *src, const fl
 #define LDDMM_PROF_HIST_RANGE  8 /* histogram matching: in-mask range (two launches) */
 #define LDDMM_PROF_HIST_COUNT  9 /* histogram matching: bin counts, totals, point table (three launches) */
 #define LDDMM_PROF_HIST_APPLY 10 /* histogram matching: intensity map */
-#define LDDMM_PROF_CLASSES  11
+#define LDDMM_PROF_ALIGN     11  /* pre-alignment: MSE and gradient pass */
+#define LDDMM_PROF_CLASSES   12
 int lddmm_profile_begin(uint32_t class_mask, int64_t min_voxels);
 int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 

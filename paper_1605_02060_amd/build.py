@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm.so")
 
-SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip", "cnn.hip", "hist.hip"]
+SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip", "cnn.hip", "hist.hip",
+           "align.hip"]
 ARCH = "gfx950"
 
 
@@ -37,8 +38,9 @@ def common_flags():
 # expression, so both give the same bits.
 CONTRACT_ON = {"flow.hip"}
 # Sources whose FP64 arithmetic restates a definition operation by operation
-# (histogram quantiles and the intensity map): no multiply-add fusion at all.
-CONTRACT_OFF = {"hist.hip"}
+# (histogram quantiles and the intensity map; affine sampling positions, where
+# a whole-number position must stay whole): no multiply-add fusion at all.
+CONTRACT_OFF = {"hist.hip", "align.hip"}
 
 
 def _compile(src):

@@ -15,6 +15,7 @@ import ctypes
 import os
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,6 +49,11 @@ class _Params(ctypes.Structure):
                 ("step", ctypes.c_double), ("guard", ctypes.c_int32),
                 ("weight", ctypes.c_double * 2), ("flags", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32)]
+
+
+class _AlignParams(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("iters", ctypes.c_int32), ("step", ctypes.c_double),
+                ("max_halvings", ctypes.c_int32)]
 
 
 class _Problem(ctypes.Structure):
@@ -102,6 +108,12 @@ def load():
     lib.lddmm_histogram_match.argtypes = [P(_Grid), vp, vp, P(_Grid), vp, vp, i32, i32, vp, vp,
                                           vp, vp, sz, vp]
     lib.lddmm_histogram_match.restype = ctypes.c_int
+    lib.lddmm_align_workspace_size.argtypes = [P(_Grid)]
+    lib.lddmm_align_workspace_size.restype = sz
+    lib.lddmm_align.argtypes = [P(_Grid), vp, P(_Grid), vp, P(_AlignParams), vp, vp, vp, sz, vp]
+    lib.lddmm_align.restype = ctypes.c_int
+    lib.lddmm_apply_affine.argtypes = [P(_Grid), vp, vp, P(_Grid), vp, i32, i32, vp, vp]
+    lib.lddmm_apply_affine.restype = ctypes.c_int
     lib.lddmm_profile_begin.argtypes = [ctypes.c_uint32, ctypes.c_int64]
     lib.lddmm_profile_begin.restype = ctypes.c_int
     lib.lddmm_profile_end.argtypes = [vp, vp, vp]
@@ -119,6 +131,7 @@ EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddm
             "lddmm_energy", "lddmm_gradient", "lddmm_apply", "lddmm_smooth_workspace_size",
             "lddmm_smooth", "lddmm_make_mask", "lddmm_mask_image",
             "lddmm_histogram_match_workspace_size", "lddmm_histogram_match",
+            "lddmm_align_workspace_size", "lddmm_align", "lddmm_apply_affine",
             "lddmm_profile_begin", "lddmm_profile_end",
             "lddmm_set_tunable", "lddmm_strerror"]
 
@@ -129,7 +142,7 @@ TUNE_FFT_ZCOLS = 3
 TUNE_STAGED_MIN_BLOCKS = 4
 
 PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
-                "other", "hist_range", "hist_count", "hist_apply"]
+                "other", "hist_range", "hist_count", "hist_apply", "align"]
 
 
 def strerror(code):
@@ -428,7 +441,78 @@ def lddmm_histogram_match(src, src_mask, ref, ref_mask, n_bins=32, n_points=8, w
     return out, points, counts
 
 
-def lddmm_profile_begin(class_mask=0x7FF, min_voxels=0):
+ALIGN_RIGID, ALIGN_AFFINE = 0, 1
+ALIGN_TRACE_COLS = 28
+
+
+def align_identity(template_shape, template_spacing, target_shape, target_spacing):
+    """Starting sampling map [B | c] (3 x 4, float64, host): B = I and the target
+    grid's centre sent to the template grid's centre."""
+    def centre(shape, h):
+        nz, ny, nx = shape
+        return 0.5 * h * np.array([nx - 1, ny - 1, nz - 1], dtype=np.float64)
+    S = np.zeros((3, 4))
+    S[:, :3] = np.eye(3)
+    S[:, 3] = centre(template_shape, template_spacing) - centre(target_shape, target_spacing)
+    return S
+
+
+def lddmm_align(template, target, mode=ALIGN_RIGID, iters=100, step=1.0, affine=None,
+                template_spacing=1.0, target_spacing=1.0, max_halvings=20, ws=None,
+                stream=None):
+    """Rigid or affine pre-alignment (Methods, Registration).  affine: starting
+    sampling map [3, 4] (device float64 tensor or host array; default: centres
+    lined up).  Returns (affine [3, 4] float64 device tensor, trace
+    [iters + 1, ALIGN_TRACE_COLS] float64 device tensor, NaN where not written)."""
+    if template.dim() != 3 or target.dim() != 3:
+        raise ValueError("template and target must be 3-D [Nz, Ny, Nx]")
+    _expect(template, tuple(template.shape), torch.float32, "template")
+    _expect(target, tuple(target.shape), torch.float32, "target")
+    dev = target.device
+    if affine is None:
+        affine = align_identity(template.shape, template_spacing, target.shape, target_spacing)
+    S = torch.as_tensor(np.asarray(affine.cpu() if torch.is_tensor(affine) else affine,
+                                   dtype=np.float64).reshape(3, 4), device=dev).contiguous()
+    gt, gr = _grid(template.shape, template_spacing), _grid(target.shape, target_spacing)
+    if ws is None:
+        nbytes = int(load().lddmm_align_workspace_size(ctypes.byref(gr)))
+        if nbytes == 0:
+            raise LddmmError(EINVAL, "lddmm_align_workspace_size")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if ws.dtype != torch.uint8 or ws.dim() != 1:
+        raise ValueError("workspace: expected a 1-D uint8 tensor")
+    trace = torch.full((max(int(iters), 0) + 1, ALIGN_TRACE_COLS), float("nan"),
+                       dtype=torch.float64, device=dev)
+    prm = _AlignParams(int(mode), int(iters), float(step), int(max_halvings))
+    _check(load().lddmm_align(ctypes.byref(gt), _ptr(template), ctypes.byref(gr), _ptr(target),
+                              ctypes.byref(prm), _ptr(S), _ptr(trace), _ptr(ws), ws.numel(),
+                              _stream(stream)), "lddmm_align")
+    return S, trace
+
+
+def lddmm_apply_affine(src, affine, dst_shape, src_spacing=1.0, dst_spacing=1.0, u=None,
+                       interp=INTERP_LINEAR, stream=None):
+    """dst(y) = src(S(y + u(y))) on a dst_shape grid (Methods, Registration:
+    phi^-1 = R^-1 A^-1 phi_10): u [3, *dst_shape] physical displacement or None;
+    linear (float32) or nearest (float32 / int32 labels)."""
+    if src.dim() != 3 or src.dtype not in (torch.int32, torch.float32):
+        raise ValueError("src: expected a 3-D float32 or int32 tensor")
+    dst_shape = tuple(int(n) for n in dst_shape)
+    _expect(u, (3,) + dst_shape, torch.float32, "u")
+    S = affine if torch.is_tensor(affine) else torch.as_tensor(np.asarray(affine, np.float64),
+                                                               device=src.device)
+    _expect(S.reshape(-1), (12,), torch.float64, "affine")
+    S = S.reshape(-1).contiguous()
+    dtype = I32 if src.dtype == torch.int32 else F32
+    dst = torch.empty(dst_shape, dtype=src.dtype, device=src.device)
+    gd, gs = _grid(dst_shape, dst_spacing), _grid(src.shape, src_spacing)
+    _check(load().lddmm_apply_affine(ctypes.byref(gd), _ptr(u), _ptr(S), ctypes.byref(gs),
+                                     _ptr(src), int(interp), dtype, _ptr(dst), _stream(stream)),
+           "lddmm_apply_affine")
+    return dst
+
+
+def lddmm_profile_begin(class_mask=0xFFF, min_voxels=0):
     """Record HIP events around every launch of the selected kernel classes
     whose grid has at least min_voxels voxels."""
     _check(load().lddmm_profile_begin(int(class_mask), int(min_voxels)), "lddmm_profile_begin")

@@ -53,14 +53,17 @@ def test_struct_layout_matches_header(tmp_path):
         "int main(){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(lddmm_params),"
         " offsetof(lddmm_params, step), offsetof(lddmm_params, weight),"
         " offsetof(lddmm_params, checkpoint_every), sizeof(lddmm_problem),"
-        " offsetof(lddmm_problem, workspace_bytes));}\n")
+        " offsetof(lddmm_problem, workspace_bytes));"
+        "printf(\"%zu %zu %zu\\n\", sizeof(lddmm_align_params), offsetof(lddmm_align_params, step),"
+        " offsetof(lddmm_align_params, max_halvings));}\n")
     exe = tmp_path / "sz"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     want = [ctypes.sizeof(L._Params), L._Params.step.offset, L._Params.weight.offset,
             L._Params.checkpoint_every.offset, ctypes.sizeof(L._Problem),
-            L._Problem.workspace_bytes.offset]
+            L._Problem.workspace_bytes.offset, ctypes.sizeof(L._AlignParams),
+            L._AlignParams.step.offset, L._AlignParams.max_halvings.offset]
     assert got == want
 
 
@@ -98,5 +101,6 @@ def test_profile_classes_match_header():
     n = int(re.search(r"#define LDDMM_PROF_CLASSES\s+(\d+)", src).group(1))
     assert len(L.PROF_CLASSES) == n
     for k, name in enumerate(("FORWARD", "BACKWARD", "FFT_X", "FFT_Y", "FFT_ZK", "FFT_YINV",
-                              "FFT_XINV", "OTHER", "HIST_RANGE", "HIST_COUNT", "HIST_APPLY")):
+                              "FFT_XINV", "OTHER", "HIST_RANGE", "HIST_COUNT", "HIST_APPLY",
+                              "ALIGN")):
         assert int(re.search(rf"#define LDDMM_PROF_{name}\s+(\d+)", src).group(1)) == k
