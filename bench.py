@@ -479,6 +479,114 @@ def bench_histmatch(args):
     print(json.dumps(res), flush=True)
 
 
+ALIGN_SLOTS = (100, 100)    # rigid, then affine descent slots per step
+ALIGN_STEP = 1.0
+# Algorithmic bytes per target voxel of one MSE/gradient pass: read the target
+# image 4, gather the template 4 (each template voxel once near the identity).
+ALIGN_ALG_BYTES = 8.0
+
+
+def align_cpu_baseline(pair, budget_s=15.0):
+    """The oracle's MSE-and-gradient evaluation (one descent slot) on the same
+    full-size masks, repeated for about budget_s (at least once)."""
+    from oracle import align as A
+    S = A.identity_map(pair.shape, SPACING, pair.shape, SPACING)
+    t0 = time.perf_counter()
+    slots = 0
+    while True:
+        A.mse_and_grad(S, pair.M0, SPACING, pair.M1, SPACING)
+        slots += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": slots * pair.M1.size / dt, "unit": "voxel-slot/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{slots} MSE + gradient evaluations (one descent slot each) of the "
+                      f"264x160x228 masks in {dt:.1f} s; FP64 NumPy, single-threaded"}
+
+
+def bench_align(args):
+    """Mask-Rigid then Mask-Affine pre-alignment (Methods, Registration) of the
+    264 x 160 x 228 atlas-like template mask to the sparse target's mask at
+    50 um: 100 rigid and 100 affine descent slots per step."""
+    import torch
+    from paper_1605_02060_amd import lddmm as L
+    from paper_1605_02060_amd import synth
+
+    L.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    log("generating atlas-like pair ...")
+    pair = synth.config_pair("atlas")
+    M0 = torch.as_tensor(pair.M0, device="cuda")
+    M1 = torch.as_tensor(pair.M1, device="cuda")
+    n1 = pair.M1.size
+    ws = torch.empty(L.load().lddmm_align_workspace_size(ctypes_grid(L, pair.shape)),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        Sr, tr_r = L.lddmm_align(M0, M1, L.ALIGN_RIGID, ALIGN_SLOTS[0], ALIGN_STEP,
+                                 template_spacing=SPACING, target_spacing=SPACING, ws=ws)
+        Sa, tr_a = L.lddmm_align(M0, M1, L.ALIGN_AFFINE, ALIGN_SLOTS[1], ALIGN_STEP, affine=Sr,
+                                 template_spacing=SPACING, target_spacing=SPACING, ws=ws)
+        return Sa, tr_r, tr_a
+
+    for w in range(max(args.warmup, 1)):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w} done")
+    L.lddmm_profile_begin(1 << L.PROF_CLASSES.index("align"), 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Sa, tr_r, tr_a = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = L.lddmm_profile_end()["align"]
+    slots = (ALIGN_SLOTS[0] + 1 + ALIGN_SLOTS[1] + 1) * args.steps
+    value = slots * n1 / elapsed
+    avg_ms = prof["ms"] / max(prof["launches"], 1)
+    achieved = ALIGN_ALG_BYTES * n1 / (avg_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = align_cpu_baseline(pair)
+    tr_r, tr_a = tr_r.cpu().numpy(), tr_a.cpu().numpy()
+    out = {
+        "metric": "alignment voxel-slots/s (MSE + gradient + guard per target voxel)",
+        "value": value,
+        "unit": "voxel-slot/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 samples, f64 sums and maps",
+        "data": "synthetic (seeded atlas-like template mask, sparse Poisson-labelled target mask)",
+        "config": {"workload": "Mask-Rigid then Mask-Affine pre-alignment of the 264x160x228 "
+                               "atlas-like mask pair at 50 um, 100 + 100 descent slots",
+                   "grid": [264, 160, 228], "spacing_mm": SPACING, "slots": list(ALIGN_SLOTS),
+                   "step": ALIGN_STEP},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_align_partials", "alg_bytes_per_voxel": ALIGN_ALG_BYTES,
+                     "avg_launch_ms": avg_ms, "launches": prof["launches"],
+                     "voxels_per_launch": n1},
+        "slot_us": 1e6 * elapsed / slots,
+        "mse": {"start": float(tr_r[0, 0]), "after_rigid": float(np.nanmin(tr_r[:, 0])),
+                "after_affine": float(np.nanmin(tr_a[:, 0]))},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def ctypes_grid(L, shape):
+    import ctypes
+    nz, ny, nx = shape
+    return ctypes.byref(L._Grid(int(nx), int(ny), int(nz), float(SPACING)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -486,10 +594,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-out", default=None)
-    ap.add_argument("--workload", choices=("atlas", "batched", "histmatch"), default="atlas",
+    ap.add_argument("--workload", choices=("atlas", "batched", "histmatch", "align"),
+                    default="atlas",
                     help="atlas (default): the single-pair atlas registration; batched: 16 "
                          "uneven pairs in one grouped launch sequence vs 16 sequential runs; "
-                         "histmatch: the Image-LDDMM histogram matching of the atlas pair")
+                         "histmatch: the Image-LDDMM histogram matching of the atlas pair; "
+                         "align: rigid + affine pre-alignment of the atlas mask pair")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("DB", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 database and exit")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "OUT"),
@@ -510,6 +620,9 @@ def main():
         return
     if args.workload == "histmatch":
         bench_histmatch(args)
+        return
+    if args.workload == "align":
+        bench_align(args)
         return
 
     import torch

@@ -29,12 +29,13 @@ namespace {
 
 constexpr int kWaves = kBlock / 64;
 constexpr int kParts = 13;              // MSE sum, r g_d p_e (9), r g_d (3)
-constexpr int kAlignBlocksMax = 1024;
+constexpr int kAlignBlocksMax = 2048;
 
 struct AlignGeom {
   int nx0, ny0, nz0;                    // template grid
   int nx1, ny1, nz1;                    // target grid
-  long long n1;
+  long long n1;                         // < 2^30 (each axis at most LDDMM_MAX_DIM)
+  FastDiv fx1, fy1;                     // division by nx1, ny1
   double h0, h1;
   double yc[3];                         // target centre (physical)
   double rho2;                          // mean squared distance of target voxels from yc
@@ -76,12 +77,15 @@ __device__ __forceinline__ void sample_grad(const float* __restrict__ f, int nx,
     return;
   const int cx = (int)cxd, cy = (int)cyd, cz = (int)czd;
   const float fx = (float)(qx - cxd), fy = (float)(qy - cyd), fz = (float)(qz - czd);
+  // corner validity per axis; 32-bit offsets (every grid has fewer than 2^30 voxels)
+  const bool vx[2] = {cx >= 0, cx + 1 < nx}, vy[2] = {cy >= 0, cy + 1 < ny},
+             vz[2] = {cz >= 0, cz + 1 < nz};
+  const int base = (cz * ny + cy) * nx + cx, sy = nx, sz = nx * ny;
   float t[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int x = cx + (k & 1), y = cy + ((k >> 1) & 1), z = cz + (k >> 2);
-    const bool ok = x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
-    t[k] = ok ? f[((long long)z * ny + y) * nx + x] : 0.f;
+    const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+    t[k] = (vx[bx] && vy[by] && vz[bz]) ? f[base + bx + by * sy + bz * sz] : 0.f;
   }
   const float ex = 1.f - fx, ey = 1.f - fy, ez = 1.f - fz;
   v = ez * (ey * (ex * t[0] + fx * t[1]) + fy * (ex * t[2] + fx * t[3])) +
@@ -124,31 +128,48 @@ __global__ __launch_bounds__(kBlock) void k_align_partials(AlignGeom g, const fl
   double acc[kParts];
 #pragma unroll
   for (int k = 0; k < kParts; ++k) acc[k] = 0.0;
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < g.n1; i += stride) {
-    const int x = (int)(i % g.nx1);
-    const long long t = i / g.nx1;
-    const int y = (int)(t % g.ny1), z = (int)(t / g.ny1);
-    // template index position (B y + c) / h0, in the definition's order of operations
-    // (this file is compiled without multiply-add fusion): positions that are
-    // whole numbers stay whole, so the cell, and the one-sided derivative on a
-    // cell face, are the same as the definition's
-    const double yx = g.h1 * x, yy = g.h1 * y, yz = g.h1 * z;
-    const double qx = (B00 * yx + B01 * yy + B02 * yz + C0) / g.h0;
-    const double qy = (B10 * yx + B11 * yy + B12 * yz + C1) / g.h0;
-    const double qz = (B20 * yx + B21 * yy + B22 * yz + C2) / g.h0;
-    const double px = yx - g.yc[0], py = yy - g.yc[1], pz = yz - g.yc[2];
-    float v, gx, gy, gz;
-    sample_grad(I0, g.nx0, g.ny0, g.nz0, qx, qy, qz, v, gx, gy, gz);
-    const double r = (double)(v - I1[i]);
-    acc[0] += r * r;
-    const double rg[3] = {r * gx * ih0, r * gy * ih0, r * gz * ih0};
+  const uint32_t stride = gridDim.x * kBlock;
+  const uint32_t n1 = (uint32_t)g.n1;
+  // two voxels per iteration (the second a grid stride further), so that both
+  // voxels' gathers are in flight together; a second voxel past the end repeats
+  // the first with zero weight
+  for (uint32_t i0 = blockIdx.x * kBlock + threadIdx.x; i0 < n1; i0 += 2 * stride) {
+    const uint32_t i1 = i0 + stride < n1 ? i0 + stride : i0;
+    const double w1 = i0 + stride < n1 ? 1.0 : 0.0;
+    double q[2][3], p[2][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      acc[1 + 3 * d] += rg[d] * px;
-      acc[2 + 3 * d] += rg[d] * py;
-      acc[3 + 3 * d] += rg[d] * pz;
-      acc[10 + d] += rg[d];
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t i = u ? i1 : i0;
+      const uint32_t t = fdiv(i, g.fx1), z = fdiv(t, g.fy1);
+      const int x = (int)(i - t * (uint32_t)g.nx1), y = (int)(t - z * (uint32_t)g.ny1);
+      // template index position (B y + c) / h0, in the definition's order of
+      // operations (no multiply-add fusion in this file): positions that are
+      // whole numbers stay whole, so the cell, and the one-sided derivative on
+      // a cell face, are the definition's
+      const double yx = g.h1 * x, yy = g.h1 * y, yz = g.h1 * z;
+      q[u][0] = (B00 * yx + B01 * yy + B02 * yz + C0) / g.h0;
+      q[u][1] = (B10 * yx + B11 * yy + B12 * yz + C1) / g.h0;
+      q[u][2] = (B20 * yx + B21 * yy + B22 * yz + C2) / g.h0;
+      p[u][0] = yx - g.yc[0];
+      p[u][1] = yy - g.yc[1];
+      p[u][2] = yz - g.yc[2];
+    }
+    float v[2], gx[2], gy[2], gz[2];
+    sample_grad(I0, g.nx0, g.ny0, g.nz0, q[0][0], q[0][1], q[0][2], v[0], gx[0], gy[0], gz[0]);
+    sample_grad(I0, g.nx0, g.ny0, g.nz0, q[1][0], q[1][1], q[1][2], v[1], gx[1], gy[1], gz[1]);
+    const float t0 = I1[i0], t1 = I1[i1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double r = (double)(v[u] - (u ? t1 : t0)) * (u ? w1 : 1.0);
+      acc[0] += r * r;
+      const double rg[3] = {r * gx[u] * ih0, r * gy[u] * ih0, r * gz[u] * ih0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        acc[1 + 3 * d] += rg[d] * p[u][0];
+        acc[2 + 3 * d] += rg[d] * p[u][1];
+        acc[3 + 3 * d] += rg[d] * p[u][2];
+        acc[10 + d] += rg[d];
+      }
     }
   }
   __shared__ double red[kWaves][kParts];
@@ -288,7 +309,8 @@ __global__ void k_align_finish(const AlignState* __restrict__ st, double* __rest
 
 struct ApplyAffArgs {
   int nx, ny, nz;                       // destination grid
-  long long n;
+  long long n;                          // < 2^30
+  FastDiv fx, fy;                       // division by nx, ny
   double hd;
   const float* u;                       // [3][n] physical displacement or null
   const double* S;                      // [12]
@@ -303,11 +325,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine(ApplyAffArgs a) {
   const double B00 = a.S[0], B01 = a.S[1], B02 = a.S[2], C0 = a.S[3];
   const double B10 = a.S[4], B11 = a.S[5], B12 = a.S[6], C1 = a.S[7];
   const double B20 = a.S[8], B21 = a.S[9], B22 = a.S[10], C2 = a.S[11];
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride) {
-    const int x = (int)(i % a.nx);
-    const long long t = i / a.nx;
-    const int y = (int)(t % a.ny), z = (int)(t / a.ny);
+  const uint32_t stride = gridDim.x * kBlock;
+  const uint32_t n = (uint32_t)a.n;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const uint32_t t = fdiv(i, a.fx), z = fdiv(t, a.fy);
+    const int x = (int)(i - t * (uint32_t)a.nx), y = (int)(t - z * (uint32_t)a.ny);
     double yx = a.hd * x, yy = a.hd * y, yz = a.hd * z;
     if (a.u) {
       yx += (double)a.u[i];
@@ -352,6 +374,8 @@ AlignGeom make_align_geom(const lddmm_grid* t0, const lddmm_grid* t1) {
   g.ny1 = t1->ny;
   g.nz1 = t1->nz;
   g.n1 = (long long)t1->nx * t1->ny * t1->nz;
+  g.fx1 = make_fastdiv((uint32_t)t1->nx);
+  g.fy1 = make_fastdiv((uint32_t)t1->ny);
   g.h0 = t0->spacing;
   g.h1 = t1->spacing;
   g.yc[0] = 0.5 * t1->spacing * (t1->nx - 1);
@@ -427,6 +451,8 @@ int lddmm_apply_affine(const lddmm_grid* dst_grid, const float* u, const double*
   a.ny = dst_grid->ny;
   a.nz = dst_grid->nz;
   a.n = nd;
+  a.fx = make_fastdiv((uint32_t)dst_grid->nx);
+  a.fy = make_fastdiv((uint32_t)dst_grid->ny);
   a.hd = dst_grid->spacing;
   a.u = u;
   a.S = affine;
