@@ -180,13 +180,14 @@ def summarize_profile(db, out_path, command):
 
 
 def library_sources_sha():
-    """SHA-256 of the HIP sources, to tell whether stored counters describe these kernels."""
-    import glob
+    """SHA-256 of the sources that define and build the measured sweep kernels
+    (the forward and backward sweeps), to tell whether stored counters describe them."""
     import hashlib
     hsh = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1605_02060_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            hsh.update(os.path.basename(p).encode())
+    for rel in ("paper_1605_02060_amd/csrc/flow.hip", "paper_1605_02060_amd/csrc/internal.h",
+                "include/lddmm.h", "paper_1605_02060_amd/build.py"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            hsh.update(rel.encode())
             hsh.update(f.read())
     return hsh.hexdigest()
 
