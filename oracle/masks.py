@@ -40,7 +40,8 @@ from scipy.spatial import cKDTree
 
 def ball_offsets(radius, h):
     """Integer offsets (dx, dy, dz) of the ball of physical radius `radius`."""
-    rr = (float(radius) / float(h)) ** 2
+    q = float(radius) / float(h)
+    rr = q * q
     m = int(np.floor(float(radius) / float(h))) + 1
     out = []
     for dz in range(-m, m + 1):
