@@ -180,15 +180,18 @@ def summarize_profile(db, out_path, command):
 
 
 def library_sources_sha():
-    """SHA-256 of the sources that define and build the measured sweep kernels
-    (the forward and backward sweeps), to tell whether stored counters describe them."""
+    """SHA-256 of what builds the measured sweep kernels (the forward and backward
+    sweeps): their sources and the compiler flags of flow.hip (paths left out), to
+    tell whether stored counters describe them."""
     import hashlib
+    from paper_1605_02060_amd import build as B
     hsh = hashlib.sha256()
     for rel in ("paper_1605_02060_amd/csrc/flow.hip", "paper_1605_02060_amd/csrc/internal.h",
-                "include/lddmm.h", "paper_1605_02060_amd/build.py"):
+                "include/lddmm.h"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             hsh.update(rel.encode())
             hsh.update(f.read())
+    hsh.update(" ".join(f for f in B.flags_for("flow.hip") if not os.path.isabs(f)).encode())
     return hsh.hexdigest()
 
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm.so")
 
 SOURCES = ["flow.hip", "fft.hip", "control.hip", "grad.hip", "runtime.hip", "cnn.hip", "hist.hip",
-           "align.hip"]
+           "align.hip", "masks.hip"]
 ARCH = "gfx950"
 
 
@@ -43,11 +43,16 @@ CONTRACT_ON = {"flow.hip"}
 CONTRACT_OFF = {"hist.hip", "align.hip"}
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def flags_for(src):
+    """Compiler flags of one source (include paths included)."""
     extra = (["-ffp-contract=on"] if src in CONTRACT_ON else
              ["-ffp-contract=off"] if src in CONTRACT_OFF else [])
-    cmd = [hipcc(), *common_flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    return [*common_flags(), *extra]
+
+
+def _compile(src):
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), *flags_for(src), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
