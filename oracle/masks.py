@@ -54,12 +54,15 @@ def ball_offsets(radius, h):
 
 def _shifted(A, o):
     """B(x) = A(x + o), background outside the grid."""
-    dx, dy, dz = o
-    nz, ny, nx = A.shape
     B = np.zeros_like(A)
-    zs, ys, xs = (slice(max(0, -d), n - max(0, d)) for d, n in ((dz, nz), (dy, ny), (dx, nx)))
-    zt, yt, xt = (slice(max(0, d), n + min(0, d)) for d, n in ((dz, nz), (dy, ny), (dx, nx)))
-    B[zs, ys, xs] = A[zt, yt, xt]
+    dst, src = [], []
+    for d, n in zip(o[::-1], A.shape):                    # (dz, nz), (dy, ny), (dx, nx)
+        lo, hi = max(0, -d), min(n, n - d)                # x with 0 <= x + d < n
+        if hi <= lo:
+            return B                                      # shifted entirely off the grid
+        dst.append(slice(lo, hi))
+        src.append(slice(lo + d, hi + d))
+    B[tuple(dst)] = A[tuple(src)]
     return B
 
 

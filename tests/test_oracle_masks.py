@@ -34,9 +34,13 @@ def test_ball_offsets():
         assert sum(c * c for c in o) * 1.21 <= 3.3 ** 2 + 1e-12
 
 
-@pytest.mark.parametrize("radius,h", [(1.0, 1.0), (2.5, 1.0), (0.125, 0.025), (0.05, 0.025)])
-def test_morphology_matches_scipy(radius, h):
-    A = _blobs((23, 26, 29), 3)
+@pytest.mark.parametrize("shape,radius,h", [((23, 26, 29), 1.0, 1.0), ((23, 26, 29), 2.5, 1.0),
+                                            ((23, 26, 29), 0.125, 0.025),
+                                            ((23, 26, 29), 0.05, 0.025),
+                                            ((3, 4, 9), 4.0, 1.0), ((6, 5, 40), 9.0, 1.0)])
+def test_morphology_matches_scipy(shape, radius, h):
+    # the last two balls are longer than some axes of the grid
+    A = _blobs(shape, 3, smooth=1.0)
     st = _ball_structure(radius, h)
     np.testing.assert_array_equal(K.erode(A, radius, h),
                                   ndimage.binary_erosion(A, st, border_value=0))
