@@ -114,6 +114,16 @@ def load():
     lib.lddmm_align.restype = ctypes.c_int
     lib.lddmm_apply_affine.argtypes = [P(_Grid), vp, vp, P(_Grid), vp, i32, i32, vp, vp]
     lib.lddmm_apply_affine.restype = ctypes.c_int
+    lib.lddmm_masks_workspace_size.argtypes = [P(_Grid)]
+    lib.lddmm_masks_workspace_size.restype = sz
+    lib.lddmm_label_mask.argtypes = [P(_Grid), vp, vp, vp]
+    lib.lddmm_label_mask.restype = ctypes.c_int
+    lib.lddmm_morphology.argtypes = [P(_Grid), vp, i32, dbl, vp, vp, sz, vp]
+    lib.lddmm_morphology.restype = ctypes.c_int
+    lib.lddmm_target_mask.argtypes = [P(_Grid), vp, ctypes.c_float, dbl, dbl, vp, vp, sz, vp]
+    lib.lddmm_target_mask.restype = ctypes.c_int
+    lib.lddmm_surface_distance.argtypes = [P(_Grid), vp, vp, vp, vp, sz, vp]
+    lib.lddmm_surface_distance.restype = ctypes.c_int
     lib.lddmm_profile_begin.argtypes = [ctypes.c_uint32, ctypes.c_int64]
     lib.lddmm_profile_begin.restype = ctypes.c_int
     lib.lddmm_profile_end.argtypes = [vp, vp, vp]
@@ -132,6 +142,8 @@ EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddm
             "lddmm_smooth", "lddmm_make_mask", "lddmm_mask_image",
             "lddmm_histogram_match_workspace_size", "lddmm_histogram_match",
             "lddmm_align_workspace_size", "lddmm_align", "lddmm_apply_affine",
+            "lddmm_masks_workspace_size", "lddmm_label_mask", "lddmm_morphology",
+            "lddmm_target_mask", "lddmm_surface_distance",
             "lddmm_profile_begin", "lddmm_profile_end",
             "lddmm_set_tunable", "lddmm_strerror"]
 
@@ -510,6 +522,72 @@ def lddmm_apply_affine(src, affine, dst_shape, src_spacing=1.0, dst_spacing=1.0,
                                      _ptr(src), int(interp), dtype, _ptr(dst), _stream(stream)),
            "lddmm_apply_affine")
     return dst
+
+
+MORPH_ERODE, MORPH_DILATE, MORPH_OPEN, MORPH_CLOSE = 0, 1, 2, 3
+MORPH_MAX_RADIUS_VOXELS = 31
+
+
+def _masks_ws(shape, spacing, ws, dev):
+    g = _grid(shape, spacing)
+    if ws is None:
+        nbytes = int(load().lddmm_masks_workspace_size(ctypes.byref(g)))
+        if nbytes == 0:
+            raise LddmmError(EINVAL, "lddmm_masks_workspace_size")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if ws.dtype != torch.uint8 or ws.dim() != 1:
+        raise ValueError("workspace: expected a 1-D uint8 tensor")
+    return g, ws
+
+
+def lddmm_label_mask(labels, stream=None):
+    """Template mask: union of the foreground labels, 1[label != 0] (Methods, Mask Generation)."""
+    if labels.dim() != 3 or labels.dtype != torch.int32:
+        raise ValueError("labels: expected a 3-D int32 tensor")
+    out = torch.empty(labels.shape, dtype=torch.float32, device=labels.device)
+    g = _grid(labels.shape, 1.0)
+    _check(load().lddmm_label_mask(ctypes.byref(g), _ptr(labels), _ptr(out), _stream(stream)),
+           "lddmm_label_mask")
+    return out
+
+
+def lddmm_morphology(mask, op, radius, spacing=1.0, ws=None, stream=None):
+    """Binary erosion / dilation / opening / closing with a ball of physical radius."""
+    if mask.dim() != 3:
+        raise ValueError("mask must be 3-D [Nz, Ny, Nx]")
+    _expect(mask, tuple(mask.shape), torch.float32, "mask")
+    g, ws = _masks_ws(mask.shape, spacing, ws, mask.device)
+    out = torch.empty_like(mask)
+    _check(load().lddmm_morphology(ctypes.byref(g), _ptr(mask), int(op), float(radius), _ptr(out),
+                                   _ptr(ws), ws.numel(), _stream(stream)), "lddmm_morphology")
+    return out
+
+
+def lddmm_target_mask(image, tau, open_radius, close_radius, spacing=1.0, ws=None, stream=None):
+    """Target mask (Methods, Mask Generation): threshold at tau, open, then close."""
+    if image.dim() != 3:
+        raise ValueError("image must be 3-D [Nz, Ny, Nx]")
+    _expect(image, tuple(image.shape), torch.float32, "image")
+    g, ws = _masks_ws(image.shape, spacing, ws, image.device)
+    out = torch.empty_like(image)
+    _check(load().lddmm_target_mask(ctypes.byref(g), _ptr(image), float(tau), float(open_radius),
+                                    float(close_radius), _ptr(out), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "lddmm_target_mask")
+    return out
+
+
+def lddmm_surface_distance(mask_a, mask_b, spacing=1.0, ws=None, stream=None):
+    """(d_H, d_M, |S_a|, |S_b|) as a float64 device tensor of 4 (Methods, Evaluation)."""
+    if mask_a.dim() != 3:
+        raise ValueError("masks must be 3-D [Nz, Ny, Nx]")
+    _expect(mask_a, tuple(mask_a.shape), torch.float32, "mask_a")
+    _expect(mask_b, tuple(mask_a.shape), torch.float32, "mask_b")
+    g, ws = _masks_ws(mask_a.shape, spacing, ws, mask_a.device)
+    out = torch.empty(4, dtype=torch.float64, device=mask_a.device)
+    _check(load().lddmm_surface_distance(ctypes.byref(g), _ptr(mask_a), _ptr(mask_b), _ptr(out),
+                                         _ptr(ws), ws.numel(), _stream(stream)),
+           "lddmm_surface_distance")
+    return out
 
 
 def lddmm_profile_begin(class_mask=0xFFF, min_voxels=0):

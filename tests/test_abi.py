@@ -13,7 +13,7 @@ from paper_1605_02060_amd import lddmm as L
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared(headers=("lddmm.h", "lddmm_cnn.h")):
+def _declared(headers=("lddmm.h", "lddmm_cnn.h", "lddmm_masks.h")):
     names = set()
     for h in headers:
         src = open(os.path.join(ROOT, "include", h)).read()
@@ -23,7 +23,8 @@ def _declared(headers=("lddmm.h", "lddmm_cnn.h")):
 
 
 def test_every_header_is_checked():
-    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["lddmm.h", "lddmm_cnn.h"]
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["lddmm.h", "lddmm_cnn.h",
+                                                                 "lddmm_masks.h"]
 
 
 def test_header_declares_the_boundary_calls():
