@@ -585,6 +585,145 @@ def bench_align(args):
     print(json.dumps(out), flush=True)
 
 
+MASK_CALLS = 20             # target mask + surface distances per step
+MASK_TAU, MASK_OPEN, MASK_CLOSE = 0.1, 0.05, 0.125   # threshold; 50 um and 125 um balls
+# Algorithmic HBM bytes per voxel of each call (FP32 inputs and outputs; the
+# bit-packed intermediates are 1/8 byte per voxel and pass):
+#  target mask      : read the image 4, write the mask 4
+#  surface distance : read both masks 8; per direction write and read the row
+#                     distances 8 and write the column distances 4 (the z pass
+#                     reads them only at surface voxels): 8 + 2 * 12
+MASK_ALG_BYTES = {"target_mask": 8.0, "surface_distance": 32.0}
+# The surface-distance y pass is integer ALU work: for every voxel and every row
+# y' of its column, a difference, a multiply-add and a minimum.
+MASK_Y_OPS = 3
+# 32-bit integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz.
+ALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def masks_image(pair):
+    """A dense image of the atlas shape with foreground grains and holes."""
+    rng = np.random.default_rng(7)
+    I = pair.I0 * (1.0 + 0.2 * rng.standard_normal(pair.shape))
+    I[rng.random(pair.shape) > 0.999] = 1.0
+    I[rng.random(pair.shape) > 0.999] = 0.0
+    return I.astype(np.float32)
+
+
+def masks_cpu_baseline(pair, I, budget_s=15.0):
+    """The oracle's target mask and surface distances of the same inputs,
+    repeated for about budget_s (at least once)."""
+    from oracle import masks as K
+    t0 = time.perf_counter()
+    calls = 0
+    while True:
+        M1 = K.target_mask(I, MASK_TAU, MASK_OPEN, MASK_CLOSE, SPACING)
+        K.surface_distances(pair.M0 > 0, M1, SPACING)
+        calls += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": calls * I.size / dt, "unit": "voxel/s", "cores": 1, "kind": "oracle",
+            "sample": f"{calls} target masks + surface distances of the 264x160x228 grid in "
+                      f"{dt:.1f} s; NumPy shifts and scipy's k-d tree, single-threaded"}
+
+
+def bench_masks(args):
+    """Mask generation and evaluation at the atlas size (Methods, Mask Generation;
+    Evaluation): the target mask by threshold, 50 um opening and 125 um closing,
+    then the Hausdorff and median surface distances to the template mask."""
+    import torch
+    from paper_1605_02060_amd import lddmm as L
+    from paper_1605_02060_amd import synth
+
+    L.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    log("generating atlas-like pair ...")
+    pair = synth.config_pair("atlas")
+    I = torch.as_tensor(masks_image(pair), device="cuda")
+    M0 = torch.as_tensor(pair.M0, device="cuda")
+    n = pair.M0.size
+    ws = torch.empty(L.load().lddmm_masks_workspace_size(ctypes_grid(L, pair.shape)),
+                     dtype=torch.uint8, device="cuda")
+
+    def step():
+        for _ in range(MASK_CALLS):
+            M1 = L.lddmm_target_mask(I, MASK_TAU, MASK_OPEN, MASK_CLOSE, spacing=SPACING, ws=ws)
+            d = L.lddmm_surface_distance(M0, M1, spacing=SPACING, ws=ws)
+        return d
+
+    for w in range(max(args.warmup, 1)):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w} done")
+    # live HIP events: the library's own around its y-pass launches (the OTHER
+    # class), torch's on the launch stream around whole calls
+    L.lddmm_profile_begin(1 << L.PROF_CLASSES.index("other"), 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ypass = L.lddmm_profile_end()["other"]
+    per = {}
+    M1 = L.lddmm_target_mask(I, MASK_TAU, MASK_OPEN, MASK_CLOSE, spacing=SPACING, ws=ws)
+    stream = torch.cuda.current_stream()
+    for name in ("target_mask", "surface_distance"):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(MASK_CALLS):
+            if name == "target_mask":
+                L.lddmm_target_mask(I, MASK_TAU, MASK_OPEN, MASK_CLOSE, spacing=SPACING, ws=ws,
+                                    stream=stream)
+            else:
+                L.lddmm_surface_distance(M0, M1, spacing=SPACING, ws=ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        avg_ms = e0.elapsed_time(e1) / MASK_CALLS
+        per[name] = {"avg_us": 1e3 * avg_ms,
+                     "GBs": MASK_ALG_BYTES[name] * n / (avg_ms * 1e-3) / 1e9}
+    y_ms = ypass["ms"] / max(ypass["launches"], 1)
+    y_ops = MASK_Y_OPS * pair.shape[1] * n                 # 3 integer ops per (voxel, row)
+    y_achieved = y_ops / (y_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = masks_cpu_baseline(pair, masks_image(pair))
+    d = d.cpu().numpy()
+    out = {
+        "metric": "mask voxels/s (target mask + two-sided surface distances)",
+        "value": MASK_CALLS * args.steps * n / elapsed,
+        "unit": "voxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bit-packed masks, int32 squared distances, f64 distances",
+        "data": "synthetic (seeded atlas-like image with grains and holes; atlas-like template mask)",
+        "config": {"workload": "target mask (threshold, 50 um opening, 125 um closing) and "
+                               "Hausdorff / median surface distances to the template mask, "
+                               f"264x160x228 at 50 um; {MASK_CALLS} of each per step",
+                   "grid": [264, 160, 228], "spacing_mm": SPACING, "tau": MASK_TAU,
+                   "open_radius_mm": MASK_OPEN, "close_radius_mm": MASK_CLOSE},
+        "roofline": {"bound": "alu", "achieved": y_achieved, "peak": ALU_INT32_PEAK_TOPS,
+                     "unit": "Tops/s", "frac": y_achieved / ALU_INT32_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_edt_y",
+                     "alg_ops_per_voxel": MASK_Y_OPS * pair.shape[1],
+                     "avg_launch_ms": y_ms, "launches": ypass["launches"],
+                     "voxels_per_launch": n},
+        "calls": per,
+        "distances_mm": {"hausdorff": float(d[0]), "median": float(d[1]),
+                         "surface_voxels": [int(d[2]), int(d[3])]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def ctypes_grid(L, shape):
     import ctypes
     nz, ny, nx = shape
@@ -598,12 +737,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-out", default=None)
-    ap.add_argument("--workload", choices=("atlas", "batched", "histmatch", "align"),
+    ap.add_argument("--workload", choices=("atlas", "batched", "histmatch", "align", "masks"),
                     default="atlas",
                     help="atlas (default): the single-pair atlas registration; batched: 16 "
                          "uneven pairs in one grouped launch sequence vs 16 sequential runs; "
                          "histmatch: the Image-LDDMM histogram matching of the atlas pair; "
-                         "align: rigid + affine pre-alignment of the atlas mask pair")
+                         "align: rigid + affine pre-alignment of the atlas mask pair; "
+                         "masks: target mask generation and surface distances")
     ap.add_argument("--summarize-profile", nargs=3, metavar=("DB", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 database and exit")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "OUT"),
@@ -627,6 +767,9 @@ def main():
         return
     if args.workload == "align":
         bench_align(args)
+        return
+    if args.workload == "masks":
+        bench_masks(args)
         return
 
     import torch

@@ -13,7 +13,8 @@
  *  - Voxels outside the grid are background for erosion and dilation.
  *  - Device pointers, asynchronous on `stream`; the workspace is device memory of
  *    lddmm_masks_workspace_size bytes, owned by the caller, no state kept
- *    between calls.  Kernel time is recorded under LDDMM_PROF_OTHER.
+ *    between calls.  The y pass of lddmm_surface_distance (its dominant
+ *    kernel) is timed under LDDMM_PROF_OTHER.
  *  - Returns LDDMM_OK, LDDMM_EINVAL (null pointer, bad grid, bad op, radius
  *    negative or not below (LDDMM_MORPH_MAX_RADIUS_VOXELS + 1) voxels,
  *    workspace too small; nothing launched) or LDDMM_EHIP.

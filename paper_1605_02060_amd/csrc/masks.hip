@@ -18,9 +18,10 @@
 // nearest voxel of the other surface is the separable minimum
 //   d2(x, y, z) = min_z' [ min_y' [ g1(x, y', z') + (y - y')^2 ] + (z - z')^2 ],
 //   g1(x, y, z) = min over surface voxels x' of row (y, z) of (x - x')^2,
-// computed as: a two-sweep nearest-feature pass along each x row, a min pass
-// along y for every voxel, and the min along z only at the voxels of the first
-// surface.  The Hausdorff distance takes the largest d2 (atomicMax); the median
+// computed as: the nearest set bit along each x row (bit scans of the packed
+// words), a min pass along y for every voxel, and the min along z only at the
+// voxels of the first surface, searched outward from the voxel and stopped once
+// the squared offset alone reaches the best value found (exact).  The Hausdorff distance takes the largest d2 (atomicMax); the median
 // counts every d2 in a histogram over the integers 0 .. max possible (counts in
 // LDS for small d2, which hold nearly all of them), and one block finds the
 // middle rank(s).  Distances are h sqrt(d2) in FP64.
@@ -212,27 +213,42 @@ __global__ __launch_bounds__(kBlock) void k_surface(MGrid g, const uint32_t* __r
   }
 }
 
-// x pass: squared distance along the row to the nearest surface voxel (two sweeps).
+// x pass: squared distance along the row to the nearest surface voxel, one
+// thread per voxel: the nearest set bit at or left of x and at or right of x,
+// found with count-leading / trailing-zero over the packed words.
 __global__ __launch_bounds__(kBlock) void k_edt_x(MGrid g, const uint32_t* __restrict__ s,
                                                   uint32_t* __restrict__ g1) {
-  const long long rows = (long long)g.ny * g.nz;
-  for (long long row = (long long)blockIdx.x * kBlock + threadIdx.x; row < rows;
-       row += (long long)gridDim.x * kBlock) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < g.n;
+       i += (long long)gridDim.x * kBlock) {
+    const long long row = i / g.nx;
+    const int x = (int)(i - row * g.nx);
     const uint32_t* sr = s + row * g.W;
-    uint32_t* out = g1 + row * g.nx;
-    int last = -1;
-    for (int x = 0; x < g.nx; ++x) {
-      if ((sr[x >> 5] >> (x & 31)) & 1u) last = x;
-      out[x] = last < 0 ? kInf : (uint32_t)((x - last) * (x - last));
-    }
-    last = -1;
-    for (int x = g.nx - 1; x >= 0; --x) {
-      if ((sr[x >> 5] >> (x & 31)) & 1u) last = x;
-      if (last >= 0) {
-        const uint32_t d = (uint32_t)((last - x) * (last - x));
-        if (d < out[x]) out[x] = d;
+    const int w0 = x >> 5, b = x & 31;
+    uint32_t best = kInf;
+    // left: bits <= b of word w0, then whole words further left
+    uint32_t m = sr[w0] & (b == 31 ? 0xFFFFFFFFu : ((2u << b) - 1u));
+    for (int w = w0;;) {
+      if (m) {
+        const int left = 32 * w + 31 - __clz(m);
+        best = (uint32_t)((x - left) * (x - left));
+        break;
       }
+      if (--w < 0) break;
+      m = sr[w];
     }
+    // right: bits >= b of word w0, then whole words further right
+    m = sr[w0] & ~((1u << b) - 1u);
+    for (int w = w0;;) {
+      if (m) {
+        const int right = 32 * w + __ffs(m) - 1;
+        const uint32_t d = (uint32_t)((right - x) * (right - x));
+        best = d < best ? d : best;
+        break;
+      }
+      if (++w >= g.W) break;
+      m = sr[w];
+    }
+    g1[i] = best;
   }
 }
 
@@ -258,20 +274,21 @@ __global__ __launch_bounds__(kBlock) void k_edt_y(MGrid g, int tx, const uint32_
   for (int k = threadIdx.x; k < g.ny * tx; k += kBlock) {
     const int y = k / tx, xl = k % tx, x = x0 + xl;
     if (x >= g.nx) continue;
+    // every row of the column (most columns never meet the surface, so an
+    // outward search with early exit does not pay here); kInf + (ny-1)^2 still
+    // fits, so no term needs a test, and a result at or above kInf is kInf
     uint32_t best = kInf;
     for (int yp = 0; yp < g.ny; ++yp) {
-      const uint32_t v = col[yp * tx + xl];
-      if (v < kInf) {
-        const uint32_t d = v + (uint32_t)((y - yp) * (y - yp));
-        best = d < best ? d : best;
-      }
+      const uint32_t e = col[yp * tx + xl] + (uint32_t)((y - yp) * (y - yp));
+      best = e < best ? e : best;
     }
-    g2[plane + (long long)y * g.nx + x] = best;
+    g2[plane + (long long)y * g.nx + x] = best < kInf ? best : kInf;
   }
 }
 
-// z pass at the voxels of surface A: d2 = min_z' g2(x, y, z') + (z - z')^2, then
-// the Hausdorff maximum and the histogram of d2.
+// z pass at the voxels of surface A (one thread per packed word, its set bits
+// only): d2 = min_z' g2(x, y, z') + (z - z')^2, searched outward from z until
+// (z - z')^2 >= d2; then the Hausdorff maximum and the histogram of d2.
 __global__ __launch_bounds__(kBlock) void k_edt_z_collect(MGrid g, const uint32_t* __restrict__ sa,
                                                           const uint32_t* __restrict__ g2,
                                                           uint32_t* __restrict__ hist,
@@ -286,37 +303,50 @@ __global__ __launch_bounds__(kBlock) void k_edt_z_collect(MGrid g, const uint32_
   }
   __syncthreads();
   const long long plane = (long long)g.nx * g.ny;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < g.n;
+  unsigned my_max = 0u, my_cnt = 0u;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < g.nwords;
        i += (long long)gridDim.x * kBlock) {
-    const long long row = i / g.nx;
-    const int x = (int)(i - row * g.nx);
-    if (!((sa[row * g.W + (x >> 5)] >> (x & 31)) & 1u)) continue;
-    const int z = (int)(row / g.ny);
-    const long long xy = i - (long long)z * plane;
-    uint32_t best = kInf;
-    for (int zp = 0; zp < g.nz; ++zp) {
-      const uint32_t v = g2[(long long)zp * plane + xy];
-      if (v < kInf) {
-        const uint32_t d = v + (uint32_t)((z - zp) * (z - zp));
-        best = d < best ? d : best;
+    uint32_t bits = sa[i];
+    if (!bits) continue;
+    const long long row = i / g.W;
+    const int wx = (int)(i - row * g.W);
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    while (bits) {
+      const int bit = __ffs(bits) - 1;
+      bits &= bits - 1u;
+      const int x = 32 * wx + bit;
+      const long long xy = (long long)y * g.nx + x;
+      uint32_t best = g2[(long long)z * plane + xy];
+      for (int d = 1; (uint32_t)(d * d) < best; ++d) {
+        const bool lo = z - d >= 0, hi = z + d < g.nz;
+        if (!lo && !hi) break;
+        const uint32_t a = lo ? g2[(long long)(z - d) * plane + xy] : kInf;
+        const uint32_t c = hi ? g2[(long long)(z + d) * plane + xy] : kInf;
+        const uint32_t m = a < c ? a : c;
+        if (m < kInf) {
+          const uint32_t e = m + (uint32_t)(d * d);
+          best = e < best ? e : best;
+        }
       }
+      // the other surface is non-empty whenever the result is used, so best < kInf
+      my_max = best > my_max ? best : my_max;
+      ++my_cnt;
+      if (best < (uint32_t)kLdsBins)
+        atomicAdd(&lh[best], 1u);
+      else if (best < nbins)
+        atomicAdd(&hist[best], 1u);
     }
-    // the other surface is non-empty whenever this pass runs, so best < kInf
-    atomicMax(&lmax, best);
-    atomicAdd(&lcnt, 1u);
-    if (best < (uint32_t)kLdsBins)
-      atomicAdd(&lh[best], 1u);
-    else if (best < nbins)
-      atomicAdd(&hist[best], 1u);
+  }
+  if (my_cnt) {
+    atomicMax(&lmax, my_max);
+    atomicAdd(&lcnt, my_cnt);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < kLdsBins && k < (int)nbins; k += kBlock)
     if (lh[k]) atomicAdd(&hist[k], lh[k]);
-  if (threadIdx.x == 0) {
-    if (lcnt) {
-      atomicMax(&scal[0], lmax);
-      atomicAdd(&scal[1], lcnt);
-    }
+  if (threadIdx.x == 0 && lcnt) {
+    atomicMax(&scal[0], lmax);
+    atomicAdd(&scal[1], lcnt);
   }
 }
 
@@ -327,7 +357,14 @@ __global__ __launch_bounds__(kBlock) void k_count_bits(const uint32_t* __restric
        i += (long long)gridDim.x * kBlock)
     c += __popc(a[i]);
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(dst, c);
+  __shared__ unsigned sw[kWaves];
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = 0;
+    for (int w = 0; w < kWaves; ++w) t += sw[w];
+    if (t) atomicAdd(dst, t);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, long long n,
@@ -337,47 +374,78 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, l
     p[i] = v;
 }
 
-// One block: Hausdorff distance and the median of the histogram of d2 over both
-// directions; out = {d_H, d_M, |S_A|, |S_B|}.
-__global__ __launch_bounds__(kBlock) void k_surface_final(const uint32_t* __restrict__ hist,
-                                                          uint32_t nbins,
-                                                          const unsigned* __restrict__ scal,
-                                                          double h, double* __restrict__ out) {
-  __shared__ unsigned long long csum[kBlock];
-  const unsigned na = scal[2], nb = scal[3];
-  const unsigned long long m = (unsigned long long)scal[1];   // distances counted, both ways
-  const uint32_t chunk = (nbins + kBlock - 1) / kBlock;
-  const uint32_t lo = threadIdx.x * chunk, hi = lo + chunk < nbins ? lo + chunk : nbins;
-  unsigned long long c = 0;
-  for (uint32_t k = lo; k < hi; ++k) c += hist[k];
-  csum[threadIdx.x] = c;
+// Sums of the histogram in tiles of kBlock bins, one block per tile.
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const uint32_t* __restrict__ hist,
+                                                      uint32_t nbins, uint32_t* __restrict__ tsum) {
+  const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t c = k < nbins ? hist[k] : 0u;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  __shared__ uint32_t wsum[kWaves];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
-    out[2] = (double)na;
-    out[3] = (double)nb;
-    if (na == 0 || nb == 0 || m == 0) {
-      out[0] = NAN;
-      out[1] = NAN;
-      return;
-    }
-    out[0] = h * sqrt((double)scal[0]);
-    // 0-based ranks of the middle value(s) in increasing d2 order
-    const unsigned long long r1 = (m - 1) / 2, r2 = m / 2;
-    double v[2] = {0.0, 0.0};
-    const unsigned long long ranks[2] = {r1, r2};
-    for (int q = 0; q < 2; ++q) {
-      unsigned long long before = 0;
-      int t = 0;
-      while (before + csum[t] <= ranks[q]) before += csum[t++];
-      uint32_t k = t * chunk;
-      for (;; ++k) {
-        before += hist[k];
-        if (before > ranks[q]) break;
-      }
-      v[q] = h * sqrt((double)k);
-    }
-    out[1] = (m & 1ull) ? v[0] : (v[0] + v[1]) / 2.0;
+    uint32_t t = 0;
+    for (int w = 0; w < kWaves; ++w) t += wsum[w];
+    tsum[blockIdx.x] = t;
   }
+}
+
+// One block: Hausdorff distance and the median of the histogram of d2 over both
+// directions; out = {d_H, d_M, |S_A|, |S_B|}.  The tile sums (in LDS) locate the
+// tiles of the middle rank(s), whose bins are then read into LDS and scanned.
+constexpr int kMaxTiles = 12800;        // >= (3 * 1023^2 + 1) / kBlock
+
+__global__ __launch_bounds__(kBlock) void k_surface_final(const uint32_t* __restrict__ hist,
+                                                          uint32_t nbins,
+                                                          const uint32_t* __restrict__ tsum_g,
+                                                          const unsigned* __restrict__ scal,
+                                                          double h, double* __restrict__ out) {
+  __shared__ uint32_t tsum[kMaxTiles];
+  __shared__ uint32_t bins[2][kBlock];
+  __shared__ uint32_t tile[2];
+  __shared__ unsigned long long before_tile[2];
+  const unsigned na = scal[2], nb = scal[3];
+  const unsigned long long m = (unsigned long long)scal[1];   // distances counted, both ways
+  const uint32_t ntiles = (nbins + kBlock - 1) / kBlock;
+  for (uint32_t t = threadIdx.x; t < ntiles; t += kBlock) tsum[t] = tsum_g[t];
+  __syncthreads();
+  const bool empty = na == 0 || nb == 0 || m == 0;
+  // 0-based ranks of the middle value(s) in increasing d2 order
+  const unsigned long long ranks[2] = {empty ? 0 : (m - 1) / 2, empty ? 0 : m / 2};
+  if (threadIdx.x < 2) {
+    unsigned long long before = 0;
+    uint32_t t = 0;
+    if (!empty)
+      while (before + tsum[t] <= ranks[threadIdx.x]) before += tsum[t++];
+    tile[threadIdx.x] = t;
+    before_tile[threadIdx.x] = before;
+  }
+  __syncthreads();
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t k = tile[q] * kBlock + threadIdx.x;
+    bins[q][threadIdx.x] = k < nbins ? hist[k] : 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  out[2] = (double)na;
+  out[3] = (double)nb;
+  if (empty) {
+    out[0] = NAN;
+    out[1] = NAN;
+    return;
+  }
+  out[0] = h * sqrt((double)scal[0]);
+  double v[2];
+  for (int q = 0; q < 2; ++q) {
+    unsigned long long before = before_tile[q];
+    int j = 0;
+    for (;; ++j) {
+      before += bins[q][j];
+      if (before > ranks[q]) break;
+    }
+    v[q] = h * sqrt((double)(tile[q] * kBlock + j));
+  }
+  out[1] = (m & 1ull) ? v[0] : (v[0] + v[1]) / 2.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_label_mask(const int32_t* __restrict__ L, long long n,
@@ -390,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_label_mask(const int32_t* __restrict
 // ------------------------------------------------------------- workspace ----
 
 struct MaskLayout {
-  size_t a, b, c, table, g1, g2, hist, scal, total;
+  size_t a, b, c, table, g1, g2, hist, tsum, scal, total;
 };
 
 MaskLayout mask_layout(const MGrid& g, uint32_t nbins) {
@@ -404,6 +472,7 @@ MaskLayout mask_layout(const MGrid& g, uint32_t nbins) {
   L.g1 = o; o += align256(sizeof(uint32_t) * (size_t)g.n);
   L.g2 = o; o += align256(sizeof(uint32_t) * (size_t)g.n);
   L.hist = o; o += align256(sizeof(uint32_t) * (size_t)nbins);
+  L.tsum = o; o += align256(sizeof(uint32_t) * (size_t)((nbins + kBlock - 1) / kBlock));
   L.scal = o; o += align256(sizeof(unsigned) * 8);
   L.total = o;
   return L;
@@ -470,7 +539,6 @@ int lddmm_morphology(const lddmm_grid* grid, const float* mask, int32_t op, doub
   hipStream_t s = (hipStream_t)stream;
   hipGetLastError();
   {
-    ProfScope ps(LDDMM_PROF_OTHER, g.n, s);
     hipLaunchKernelGGL(k_pack, dim3((unsigned)(g.ny * g.nz)), dim3(64), 0, s, g, mask, (int)SRC_MASK,
                        0.f, a);
     if (op == LDDMM_MORPH_ERODE || op == LDDMM_MORPH_DILATE) {
@@ -502,7 +570,6 @@ int lddmm_target_mask(const lddmm_grid* grid, const float* image, float tau, dou
   hipStream_t s = (hipStream_t)stream;
   hipGetLastError();
   {
-    ProfScope ps(LDDMM_PROF_OTHER, g.n, s);
     hipLaunchKernelGGL(k_pack, dim3((unsigned)(g.ny * g.nz)), dim3(64), 0, s, g, image,
                        (int)SRC_THRESHOLD, tau, a);
     const double ro = open_radius / grid->spacing, rc = close_radius / grid->spacing;
@@ -529,6 +596,7 @@ int lddmm_surface_distance(const lddmm_grid* grid, const float* mask_a, const fl
   uint32_t* g1 = reinterpret_cast<uint32_t*>(ws + L.g1);
   uint32_t* g2 = reinterpret_cast<uint32_t*>(ws + L.g2);
   uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+  uint32_t* tsum = reinterpret_cast<uint32_t*>(ws + L.tsum);
   unsigned* scal = reinterpret_cast<unsigned*>(ws + L.scal);
   hipStream_t s = (hipStream_t)stream;
   const unsigned rows = (unsigned)(g.ny * g.nz);
@@ -536,7 +604,6 @@ int lddmm_surface_distance(const lddmm_grid* grid, const float* mask_a, const fl
   const unsigned ytiles = (unsigned)(g.nz * ((g.nx + tx - 1) / tx));
   hipGetLastError();
   {
-    ProfScope ps(LDDMM_PROF_OTHER, g.n, s);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nbins)), dim3(kBlock), 0, s, hist,
                        (long long)nbins, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, scal, 8ll, 0u);
@@ -551,13 +618,18 @@ int lddmm_surface_distance(const lddmm_grid* grid, const float* mask_a, const fl
     for (int dir = 0; dir < 2; ++dir) {
       const uint32_t* from = dir == 0 ? c : a;       // surface whose voxels are measured
       const uint32_t* to = dir == 0 ? a : c;         // surface measured against
-      hipLaunchKernelGGL(k_edt_x, dim3(blocks_for(rows)), dim3(kBlock), 0, s, g, to, g1);
-      hipLaunchKernelGGL(k_edt_y, dim3(ytiles), dim3(kBlock), sizeof(uint32_t) * g.ny * tx, s, g,
-                         tx, g1, g2);
-      hipLaunchKernelGGL(k_edt_z_collect, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, from, g2,
-                         hist, nbins, scal);
+      hipLaunchKernelGGL(k_edt_x, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, to, g1);
+      {
+        ProfScope ps(LDDMM_PROF_OTHER, g.n, s);     // the y pass: the dominant kernel
+        hipLaunchKernelGGL(k_edt_y, dim3(ytiles), dim3(kBlock), sizeof(uint32_t) * g.ny * tx, s,
+                           g, tx, g1, g2);
+      }
+      hipLaunchKernelGGL(k_edt_z_collect, dim3(blocks_for(g.nwords)), dim3(kBlock), 0, s, g, from,
+                         g2, hist, nbins, scal);
     }
-    hipLaunchKernelGGL(k_surface_final, dim3(1), dim3(kBlock), 0, s, hist, nbins, scal,
+    hipLaunchKernelGGL(k_tile_sums, dim3((nbins + kBlock - 1) / kBlock), dim3(kBlock), 0, s, hist,
+                       nbins, tsum);
+    hipLaunchKernelGGL(k_surface_final, dim3(1), dim3(kBlock), 0, s, hist, nbins, tsum, scal,
                        grid->spacing, out);
   }
   return launch_status();
