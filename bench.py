@@ -35,6 +35,8 @@ B_ALG_PATH = 162.0          # per voxel-timestep per iteration, whole path
 
 LEVELS = 3
 T = 10
+FLAGS = 0                   # library flags of the atlas workload (atlas-rk4: LDDMM_FLAG_RK4)
+INTEGRATOR = "euler"        # the oracle's name for the same flow integrator
 ITERS = (200, 200, 200)
 SPACING = 0.05              # mm: the 264 x 160 x 228 grid is the atlas at 50 um
 ALPHA, GAMMA, SIGMA = 0.02, 1.0, 1.0
@@ -47,8 +49,11 @@ def log(msg):
 
 
 def workload_config():
+    integ = "first-order semi-Lagrangian" if FLAGS == 0 else "fourth-order Runge-Kutta"
     return {"workload": "atlas-like 264x160x228 masked LDDMM (Mask-LDDMM channel), "
-                        "3-level pyramid 4x/2x/1x, T=10, 200 iterations/level",
+                        f"3-level pyramid 4x/2x/1x, T={T} ({integ} departure points), "
+                        "200 iterations/level",
+            "integrator": INTEGRATOR,
             "grid": [264, 160, 228], "comp_grid_finest": [280, 160, 240],
             "levels": LEVELS, "timesteps": T, "iters_per_level": list(ITERS),
             "spacing_mm": SPACING, "alpha": ALPHA, "gamma": GAMMA, "sigma": SIGMA,
@@ -69,7 +74,8 @@ def work_units(shape):
 def cpu_baseline(pair, budget_s=20.0):
     """The FP64 oracle on a bounded sample: iterations of the coarsest level."""
     from oracle import lddmm as O
-    prm = O.Params(alpha=ALPHA, gamma=GAMMA, sigma=SIGMA, T=T, step=STEP, spacing=SPACING)
+    prm = O.Params(alpha=ALPHA, gamma=GAMMA, sigma=SIGMA, T=T, step=STEP, spacing=SPACING,
+                   integrator=INTEGRATOR)
     prob = O.Problem(pair.M0, pair.M1, pair.MI0, pair.MI1)
     J0u, J1u = prob.channels()
     grids = O.level_grids(pair.shape, LEVELS)
@@ -737,9 +743,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-out", default=None)
-    ap.add_argument("--workload", choices=("atlas", "batched", "histmatch", "align", "masks"),
+    ap.add_argument("--workload", choices=("atlas", "atlas-rk4", "batched", "histmatch", "align",
+                                           "masks"),
                     default="atlas",
-                    help="atlas (default): the single-pair atlas registration; batched: 16 "
+                    help="atlas (default): the single-pair atlas registration; atlas-rk4: the "
+                         "same with the paper's integrator (RK4, T=4); batched: 16 "
                          "uneven pairs in one grouped launch sequence vs 16 sequential runs; "
                          "histmatch: the Image-LDDMM histogram matching of the atlas pair; "
                          "align: rigid + affine pre-alignment of the atlas mask pair; "
@@ -771,6 +779,9 @@ def main():
     if args.workload == "masks":
         bench_masks(args)
         return
+    if args.workload == "atlas-rk4":
+        global T, FLAGS, INTEGRATOR
+        T, INTEGRATOR = 4, "rk4"
 
     import torch
     from paper_1605_02060_amd import lddmm as L
@@ -778,13 +789,15 @@ def main():
 
     L.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if INTEGRATOR == "rk4":
+        FLAGS = L.FLAG_RK4
     log("generating atlas-like pair ...")
     pair = synth.config_pair("atlas")
     dev = "cuda"
     tt = lambda a: torch.as_tensor(a, device=dev)
     M0, M1, MI0, MI1 = tt(pair.M0), tt(pair.M1), tt(pair.MI0), tt(pair.MI1)
     prm = L.Params(alpha=ALPHA, gamma=GAMMA, sigma=SIGMA, T=T, n_levels=LEVELS, iters=ITERS,
-                   step=STEP, guard=GUARD, weight=(1.0, 0.0))
+                   step=STEP, guard=GUARD, weight=(1.0, 0.0), flags=FLAGS)
     P = L.lddmm_comp_grid(pair.shape, prm, 0, SPACING)
     ws = L.workspace(pair.shape, prm, SPACING, dev)
     n_fine = P[0] * P[1] * P[2]
@@ -847,7 +860,8 @@ def main():
         "data": "synthetic (seeded atlas-like template, sparse Poisson-labelled warped target)",
         "config": workload_config(),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dominant),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(dominant) if FLAGS == 0 else None,
                      "kernel": f"k_{dominant}", "alg_bytes_per_voxel": ALG_BYTES[dominant],
                      "measured_on": "finest-level launches (280x160x240 grid) of the timed steps",
                      "avg_launch_ms": avg_ms, "launches": live["launches"],
