@@ -568,9 +568,18 @@ __device__ __forceinline__ void zK_body(const FftPair& f, int bx, int ky, int co
   tile_store<true>(sm, base, lgTX, N, ls, hx, kx0, zs);
 }
 
+// One block per tile, in an XCD-aware order: consecutive block indices go to
+// the accelerator dies in turn, so block L takes tile (L mod 8) * (tiles / 8) +
+// L / 8 and every die works through a contiguous run of tiles.  Neighbouring kx
+// tiles (two 8-column tiles share each 128-byte line of a z row) then run at
+// the same time behind the same L2 instead of fetching each line twice.
 template <int EMAX>
 __global__ __launch_bounds__(kBlock) void k_fft_z_K(FftPair f) {
-  zK_body<EMAX>(f, blockIdx.x, blockIdx.y, blockIdx.z);
+  const uint32_t total = gridDim.x;
+  uint32_t t = blockIdx.x;
+  if ((total % kXCD) == 0) t = (t % kXCD) * (total / kXCD) + t / kXCD;
+  const int bx = (int)(t % (uint32_t)f.nbx_z), r = (int)(t / (uint32_t)f.nbx_z);
+  zK_body<EMAX>(f, bx, r % f.g.ny, r / f.g.ny);
 }
 
 template <int EMAX>
@@ -746,7 +755,7 @@ void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t
 }
 
 void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s) {
-  const dim3 grid(f.nbx_z, f.g.ny, 3);
+  const dim3 grid(f.nbx_z * f.g.ny * 3);
   EMAX_SWITCH(L.ez,
     hipLaunchKernelGGL(k_fft_z_K<8>, grid, dim3(kBlock), L.z_lds, s, f),
     hipLaunchKernelGGL(k_fft_z_K<16>, grid, dim3(kBlock), L.z_lds, s, f),
