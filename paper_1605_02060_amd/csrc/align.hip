@@ -423,7 +423,7 @@ int lddmm_align(const lddmm_grid* template_grid, const float* template_image,
   AlignState* st = reinterpret_cast<AlignState*>(ws + align_state_offset(nblk));
   const AlignGeom g = make_align_geom(template_grid, target_grid);
   hipStream_t s = (hipStream_t)stream;
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   hipLaunchKernelGGL(k_align_init, dim3(1), dim3(64), 0, s, affine, params->step, st);
   for (int slot = 0; slot <= params->iters; ++slot) {
     {
@@ -466,7 +466,7 @@ int lddmm_apply_affine(const lddmm_grid* dst_grid, const float* u, const double*
   a.dst = dst;
   long long blocks = (nd + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   hipLaunchKernelGGL(k_apply_affine, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream,
                      a);
   return launch_status();

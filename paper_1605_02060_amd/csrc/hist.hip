@@ -429,7 +429,7 @@ int lddmm_histogram_match(const lddmm_grid* src_grid, const float* src, const fl
   HistTable* table = reinterpret_cast<HistTable*>(ws + L.table);
   const HistImage a{src, src_mask, ns}, b{ref, ref_mask, nr};
   hipStream_t s = (hipStream_t)stream;
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   {
     ProfScope ps(LDDMM_PROF_HIST_RANGE, ns + nr, s);
     hipLaunchKernelGGL(k_hist_range_part, dim3(nblk, 2), dim3(kBlock), 0, s, a, b, plo, phi, pn);
@@ -458,7 +458,7 @@ int lddmm_mask_image(const lddmm_grid* grid, const float* image, const float* ma
   if (n < 0 || !image || !mask || !out) return LDDMM_EINVAL;
   long long blocks = (n + kBlock - 1) / kBlock;
   if (blocks > 8192) blocks = 8192;
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   hipLaunchKernelGGL(k_mask_image, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream,
                      image, mask, n, out);
   return launch_status();

@@ -517,7 +517,7 @@ size_t lddmm_masks_workspace_size(const lddmm_grid* grid) {
 int lddmm_label_mask(const lddmm_grid* grid, const int32_t* labels, float* mask, void* stream) {
   if (grid_voxels(grid) < 0 || !labels || !mask) return LDDMM_EINVAL;
   const MGrid g = make_mgrid(grid);
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   hipLaunchKernelGGL(k_label_mask, dim3(blocks_for(g.n)), dim3(kBlock), 0, (hipStream_t)stream,
                      labels, g.n, mask);
   return launch_status();
@@ -537,7 +537,7 @@ int lddmm_morphology(const lddmm_grid* grid, const float* mask, int32_t op, doub
   int8_t* table = reinterpret_cast<int8_t*>(ws + L.table);
   const double rho = radius / grid->spacing;
   hipStream_t s = (hipStream_t)stream;
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   {
     hipLaunchKernelGGL(k_pack, dim3((unsigned)(g.ny * g.nz)), dim3(64), 0, s, g, mask, (int)SRC_MASK,
                        0.f, a);
@@ -568,7 +568,7 @@ int lddmm_target_mask(const lddmm_grid* grid, const float* image, float tau, dou
   uint32_t* b = reinterpret_cast<uint32_t*>(ws + L.b);
   int8_t* table = reinterpret_cast<int8_t*>(ws + L.table);
   hipStream_t s = (hipStream_t)stream;
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   {
     hipLaunchKernelGGL(k_pack, dim3((unsigned)(g.ny * g.nz)), dim3(64), 0, s, g, image,
                        (int)SRC_THRESHOLD, tau, a);
@@ -602,7 +602,7 @@ int lddmm_surface_distance(const lddmm_grid* grid, const float* mask_a, const fl
   const unsigned rows = (unsigned)(g.ny * g.nz);
   const int tx = edt_tile_x(g.ny);
   const unsigned ytiles = (unsigned)(g.nz * ((g.nx + tx - 1) / tx));
-  hipGetLastError();
+  (void)hipGetLastError();   // clear an earlier error: the status returned is these launches'
   {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nbins)), dim3(kBlock), 0, s, hist,
                        (long long)nbins, 0u);

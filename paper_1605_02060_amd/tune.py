@@ -3,7 +3,7 @@
 The library exposes three process-wide launch-shape tunables (sweep blocks,
 x-pass LDS budget, y/z tile columns); none of them changes a result, only the
 speed.  `autotune` times a short fixed-step registration of the caller's own
-problems for each candidate value, one tunable at a time (coordinate search from
+problems (their pyramid, a few iterations per level) for each candidate value, one tunable at a time (coordinate search from
 the defaults), keeps the fastest, and caches the choice in a JSON file keyed by
 architecture, T and the computational grids.  `apply` sets a cached choice.
 """
@@ -94,9 +94,11 @@ def autotune(pairs, params: L.Params, iters=3, repeats=2, use_cache=True, verbos
         choice = {int(w): v for w, v in cache[k].items()}
         set_all(choice)
         return choice
+    # the caller's pyramid with a few iterations per level: a launch shape can
+    # help the finest grid and hurt the coarse ones (the staged-sweep threshold)
     short = L.Params(alpha=params.alpha, gamma=params.gamma, sigma=params.sigma, T=params.T,
-                     n_levels=1, iters=(iters,), step=params.step, guard=False,
-                     weight=params.weight)
+                     n_levels=params.n_levels, iters=(iters,) * params.n_levels,
+                     step=params.step, guard=False, weight=params.weight, flags=params.flags)
     wss = [L.workspace(s, short, d.get("spacing", 1.0), d["M0"].device)
            for s, d in zip(shapes, pairs)]
     choice = dict(DEFAULTS)
