@@ -49,6 +49,20 @@ def test_morphology_matches_oracle(shape, radius, h):
         np.testing.assert_array_equal(got > 0, ref(A, radius, h), err_msg=str(op))
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 33), (1, 3, 1), (2, 1, 64), (5, 1, 1)])
+def test_thin_grids(shape):
+    # grids one voxel thick along one or two axes: every ball row but the centre
+    # one leaves the grid
+    say(f"morphology and surfaces on a thin grid {shape}")
+    rng = np.random.default_rng(8)
+    A = rng.random(shape) > 0.4
+    B = rng.random(shape) > 0.5
+    for op, ref in OPS:
+        got = L.lddmm_morphology(t(A), op, 2.0).cpu().numpy()
+        np.testing.assert_array_equal(got > 0, ref(A, 2.0, 1.0), err_msg=str(op))
+    _check_distances(A, B, 1.0)
+
+
 def test_morphology_largest_radius():
     say("morphology r = 31 voxels, 70 wide")
     A = _blobs((8, 9, 70), 2, p=0.3, smooth=1.0)
