@@ -355,6 +355,12 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 #define LDDMM_TUNE_STAGED_MIN_BLOCKS 4
 int lddmm_set_tunable(int32_t which, int32_t value);
 
+/* Device copy of n floats, src -> dst (device, not overlapping): the library's
+ * copy kernel, the one that moves v between pyramid levels; with a large n it is
+ * also a probe of the attainable memory bandwidth.  Async; LDDMM_EINVAL for a
+ * null pointer with n > 0 or n < 0. */
+int lddmm_copy(const float *src, float *dst, int64_t n, void *stream);
+
 /* Human-readable text of a status code (static storage). */
 const char *lddmm_strerror(int code);
 

@@ -1146,6 +1146,14 @@ int lddmm_make_mask(const lddmm_grid* grid, const float* image, float tau, float
   return hip_status();
 }
 
+int lddmm_copy(const float* src, float* dst, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!src || !dst))) return LDDMM_EINVAL;
+  if (n == 0) return LDDMM_OK;
+  (void)hipGetLastError();
+  launch_copy(src, dst, (long long)n, (hipStream_t)stream);
+  return hip_status();
+}
+
 int lddmm_set_tunable(int32_t which, int32_t value) {
   if (which == LDDMM_TUNE_SWEEP_BLOCKS) {
     if (value < 1) return LDDMM_EINVAL;

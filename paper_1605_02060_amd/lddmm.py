@@ -128,6 +128,8 @@ def load():
     lib.lddmm_profile_begin.restype = ctypes.c_int
     lib.lddmm_profile_end.argtypes = [vp, vp, vp]
     lib.lddmm_profile_end.restype = ctypes.c_int
+    lib.lddmm_copy.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.lddmm_copy.restype = ctypes.c_int
     lib.lddmm_set_tunable.argtypes = [i32, i32]
     lib.lddmm_set_tunable.restype = ctypes.c_int
     lib.lddmm_strerror.argtypes = [ctypes.c_int]
@@ -145,7 +147,7 @@ EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddm
             "lddmm_masks_workspace_size", "lddmm_label_mask", "lddmm_morphology",
             "lddmm_target_mask", "lddmm_surface_distance",
             "lddmm_profile_begin", "lddmm_profile_end",
-            "lddmm_set_tunable", "lddmm_strerror"]
+            "lddmm_set_tunable", "lddmm_copy", "lddmm_strerror"]
 
 TUNE_SWEEP_BLOCKS = 0
 TUNE_FFT_X_ELEMS = 1
@@ -607,6 +609,15 @@ def lddmm_profile_end():
                                     ctypes.cast(vox, ctypes.c_void_p)), "lddmm_profile_end")
     return {name: {"ms": ms[k], "launches": cnt[k], "voxels": vox[k]}
             for k, name in enumerate(PROF_CLASSES)}
+
+
+def lddmm_copy(src, dst, stream=None):
+    """dst <- src (float32 device tensors of the same size) with the library's copy kernel."""
+    if src.dtype != torch.float32 or dst.dtype != torch.float32 or src.numel() != dst.numel():
+        raise ValueError("lddmm_copy: float32 tensors of the same size expected")
+    _check(load().lddmm_copy(_ptr(src), _ptr(dst), int(src.numel()), _stream(stream)),
+           "lddmm_copy")
+    return dst
 
 
 def lddmm_set_tunable(which, value):
