@@ -60,10 +60,12 @@ def workload_config():
             "step": STEP, "guard": GUARD, "weights": [1.0, 0.0]}
 
 
-def attainable_bandwidth(torch, L, nbytes=1 << 30, reps=10):
-    """HBM bandwidth the library's copy kernel reaches on 1 GiB (read + write bytes /
-    time), timed with events on its stream: the ceiling a streaming kernel can
-    expect in practice, beside the published peak."""
+def attainable_bandwidth(torch, L, nbytes=None, reps=10):
+    """HBM bandwidth the library's copy kernel reaches (read + write bytes / time),
+    timed with events on its stream: the ceiling a streaming kernel can expect in
+    practice, beside the published peak.  The copy is the size of the finest-level
+    velocity (COPY_FLOATS), the same copy the counter calibration uses."""
+    nbytes = 4 * COPY_FLOATS if nbytes is None else nbytes
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
@@ -239,7 +241,8 @@ def stored_traffic(kernel):
 
 
 # Calibration: the copy of the finest-level velocity buffer between pyramid levels
-# (k_copy of 3 T |P| floats) reads and writes exactly this many bytes.
+# (k_copy of 3 T |P| floats; the bandwidth probe copies the same size) reads and
+# writes exactly this many bytes.
 COPY_FLOATS = 3 * T * 280 * 160 * 240
 FINEST_VOXELS = 280 * 160 * 240
 
@@ -265,10 +268,14 @@ def compute_traffic(fetch_db, write_db, out_path):
     per = {}
     for tag, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         rows = per_kernel(db, counter)
-        copy = [v for (name, grid), items in rows.items() if name == "k_copy" and grid == COPY_FLOATS
+        # the copies of v between pyramid levels share one launch shape: the
+        # finest-level copy is the group of the longest ones
+        allc = [(d, v) for (name, grid), items in rows.items() if name == "k_copy"
                 for d, v in items]
-        if not copy:
-            raise SystemExit(f"no finest-level k_copy dispatch in {db}")
+        if not allc:
+            raise SystemExit(f"no k_copy dispatch in {db}")
+        dmax = max(d for d, v in allc)
+        copy = [v for d, v in allc if d >= 0.7 * dmax]
         factors[tag] = 4.0 * COPY_FLOATS / (1024.0 * sum(copy) / len(copy))
         per[tag] = rows
     out["fetch_factor"], out["write_factor"] = factors["fetch"], factors["write"]
