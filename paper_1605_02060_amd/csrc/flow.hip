@@ -849,7 +849,8 @@ void launch_fill(float* p, long long n, float val, hipStream_t s) {
 }
 
 // Device copy: 16-byte loads and stores when both buffers are 16-byte aligned
-// (the tail, and unaligned buffers, element by element), on a bounded grid.
+// (the tail, and unaligned buffers, element by element); one 16-byte element per
+// thread over the whole grid (the loop only covers grids beyond the launch cap).
 __global__ __launch_bounds__(kBlock) void k_copy(const float* __restrict__ a, float* __restrict__ b,
                                                  long long n) {
   const long long stride = (long long)gridDim.x * kBlock;
@@ -867,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(const float* __restrict__ a, fl
 
 void launch_copy(const float* src, float* dst, long long n, hipStream_t s) {
   long long blocks = (n / 4 + kBlock - 1) / kBlock;
-  blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
+  blocks = blocks < 1 ? 1 : (blocks > (1LL << 30) ? (1LL << 30) : blocks);
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, n);
 }
 
