@@ -513,7 +513,7 @@ __device__ __forceinline__ float dstencil_v(float plus, float minus, float cente
   return (vp - vm) * sc;
 }
 
-template <int NC, bool HAS_U>
+template <int NC, bool HAS_U, bool RK4 = false>
 __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block) {
   __shared__ float su[3][kBRing][kBYH][kBXH];
   __shared__ float sj[NC][3][kBYJ][kBXJ];
@@ -571,7 +571,8 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
       const uint32_t i = (uint32_t)((z * ny + y) * nx + x);
       const int s0 = z % kBRing;
       if (HAS_U) {
-        const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
+        float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
+        if (RK4) rk4_mean(V0, V1, V2, g, x, y, z, dt * ih, vx, vy, vz);
         float ux = dt * vx, uy = dt * vy, uz = dt * vz;
         int cx, cy, cz;
         float fx, fy, fz;
@@ -632,9 +633,25 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
   if (threadIdx.x == 0) a.partDet[block] = m;
 }
 
-template <int NC, bool HAS_U>
+template <int NC, bool HAS_U, bool RK4>
 __global__ __launch_bounds__(kBlock) void k_backward_staged(BwdArgs a) {
-  backward_staged_body<NC, HAS_U>(a, blockIdx.x);
+  backward_staged_body<NC, HAS_U, RK4>(a, blockIdx.x);
+}
+
+template <bool RK4>
+static void staged_dispatch(const BwdArgs& a, bool hu, hipStream_t s) {
+  const dim3 grid(backward_partials(a.g));
+  if (a.nch == 2) {
+    if (hu)
+      hipLaunchKernelGGL((k_backward_staged<2, true, RK4>), grid, dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_backward_staged<2, false, RK4>), grid, dim3(kBlock), 0, s, a);
+  } else {
+    if (hu)
+      hipLaunchKernelGGL((k_backward_staged<1, true, RK4>), grid, dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_backward_staged<1, false, RK4>), grid, dim3(kBlock), 0, s, a);
+  }
 }
 
 // Batched body-force step: every problem gets backward_partials(g) blocks and
@@ -681,18 +698,10 @@ static void bwd_dispatch(const BwdArgs& a, hipStream_t s) {
 void launch_backward(const BwdArgs& a, hipStream_t s) {
   const bool hu = a.j >= 0, uz = (a.u_next == nullptr), hb = (a.jb >= 0 && a.jb < a.T);
   if (hb && !uz && a.staged) {
-    const dim3 grid(backward_partials(a.g));
-    if (a.nch == 2) {
-      if (hu)
-        hipLaunchKernelGGL((k_backward_staged<2, true>), grid, dim3(kBlock), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_backward_staged<2, false>), grid, dim3(kBlock), 0, s, a);
-    } else {
-      if (hu)
-        hipLaunchKernelGGL((k_backward_staged<1, true>), grid, dim3(kBlock), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_backward_staged<1, false>), grid, dim3(kBlock), 0, s, a);
-    }
+    if (a.rk4)
+      staged_dispatch<true>(a, hu, s);
+    else
+      staged_dispatch<false>(a, hu, s);
     return;
   }
   if (a.rk4) {

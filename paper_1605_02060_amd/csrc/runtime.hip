@@ -455,7 +455,8 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
     a.st = c.st;
     a.need_mode = need_mode;
     a.rk4 = k.rk4;
-    a.staged = backward_staged(L.g) && !k.rk4;     // the staged kernel is first-order
+    // the same choice as backward_partials(), which sizes the min-det reduction
+    a.staged = backward_staged(L.g);
     if (a.j < 0 && a.jb < 0) continue;
     {
       ProfScope ps(LDDMM_PROF_BACKWARD, n, s);

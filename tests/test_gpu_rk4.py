@@ -119,3 +119,32 @@ def test_rk4_rejected_where_not_defined():
     v = torch.zeros((2, 3, 16, 16, 16), device=DEV)
     with pytest.raises(L.LddmmError):
         L.lddmm_gradient(d["M0"], d["M1"], None, None, v, prm, kind=L.GRAD_L2)
+
+
+def test_rk4_staged_backward_is_bitwise_the_grid_stride_one():
+    # the LDS-staged body-force sweep and the grid-stride one take the same RK4
+    # departure points; forcing each in turn must give the same bits everywhere,
+    # including the min-det trace column, whose reduction is sized by the
+    # staged/grid-stride choice, and the oracle's trajectory
+    say("rk4 staged vs grid-stride backward, ragged 20x27x33")
+    p = synth.blob_pair((20, 27, 33), 9, max_disp=2.0, sigma=(2.0, 4.0))
+    h = 0.1
+    prm = O.Params(T=4, iters=(6,), step=0.02, spacing=h, integrator="rk4", weight=(1.0, 0.5))
+    args = (t(p.M0), t(p.M1), t(p.MI0), t(p.MI1))
+    out = {}
+    try:
+        for name, thr in (("staged", 1), ("grid", 1 << 30)):
+            L.lddmm_set_tunable(L.TUNE_STAGED_MIN_BLOCKS, thr)
+            res = L.lddmm_register(*args, params=_lp(prm), spacing=h)
+            torch.cuda.synchronize()
+            out[name] = {k: host(res[k]) for k in ("v", "phi10", "phi01", "trace")}
+    finally:
+        L.lddmm_set_tunable(L.TUNE_STAGED_MIN_BLOCKS, 2048)
+    for k in ("v", "phi10", "phi01", "trace"):
+        np.testing.assert_array_equal(out["staged"][k], out["grid"][k], err_msg=k)
+    ref = O.register(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm)
+    tr, rt = out["staged"]["trace"], np.array(ref.trace)
+    np.testing.assert_array_equal(tr[:, 6], rt[:, 6])
+    fin = np.isfinite(rt[:, 0])
+    assert np.all(np.abs(tr[fin, 0] - rt[fin, 0]) <= 1e-5 * np.abs(rt[fin, 0]))
+    assert np.abs(out["staged"]["phi10"] - ref.phi10).max() / h < 1e-4
