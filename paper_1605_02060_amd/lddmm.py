@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 import torch
@@ -342,11 +342,18 @@ def lddmm_register_batched(pairs, params: Params = None, vs=None, wss=None, want
     return results, code
 
 
+def _single_level(params: Params) -> Params:
+    """The parameters as lddmm_energy / lddmm_gradient use them: one level (the
+    library ignores n_levels there), so v lives on the single-level grid."""
+    return replace(params, n_levels=1, iters=(int(params.iters[0]) if params.iters else 0,))
+
+
 def lddmm_energy(M0, M1, MI0, MI1, v, params: Params, spacing=1.0, ws=None, stream=None):
-    """(E, R, D, image SSD) of v as a float64 device tensor of 4."""
+    """(E, R, D, image SSD) of v ([T,3,P] on the single-level computational grid,
+    n_levels ignored) as a float64 device tensor of 4."""
     ws = ws if ws is not None else workspace(M0.shape, params, spacing, M0.device)
     out = torch.empty(4, dtype=torch.float64, device=M0.device)
-    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=params)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=_single_level(params))
     _check(load().lddmm_energy(ctypes.byref(pr), ctypes.byref(params.c()), _ptr(out),
                                _stream(stream)), "lddmm_energy")
     return out
@@ -354,11 +361,12 @@ def lddmm_energy(M0, M1, MI0, MI1, v, params: Params, spacing=1.0, ws=None, stre
 
 def lddmm_gradient(M0, M1, MI0, MI1, v, params: Params, kind=GRAD_V, spacing=1.0, ws=None,
                    stream=None):
-    """Gradient of E at v ([T,3,P]) and (E, R, D, image SSD)."""
+    """Gradient of E at v ([T,3,P] on the single-level computational grid, n_levels
+    ignored) and (E, R, D, image SSD)."""
     ws = ws if ws is not None else workspace(M0.shape, params, spacing, M0.device)
     out = torch.empty(4, dtype=torch.float64, device=M0.device)
     grad = torch.empty_like(v)
-    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=params)
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=_single_level(params))
     _check(load().lddmm_gradient(ctypes.byref(pr), ctypes.byref(params.c()), int(kind),
                                  _ptr(grad), _ptr(out), _stream(stream)), "lddmm_gradient")
     return grad, out

@@ -105,3 +105,21 @@ def test_profile_classes_match_header():
                               "FFT_XINV", "OTHER", "HIST_RANGE", "HIST_COUNT", "HIST_APPLY",
                               "ALIGN")):
         assert int(re.search(rf"#define LDDMM_PROF_{name}\s+(\d+)", src).group(1)) == k
+
+
+def test_energy_and_gradient_take_v_on_the_single_level_grid():
+    # the library evaluates energy and gradient on one level whatever n_levels
+    # says, so the binding checks v against the single-level grid
+    import torch
+    N = (12, 12, 29)
+    M = torch.zeros(N)
+    prm = L.Params(T=2, n_levels=3, iters=(1, 1, 1))
+    P2 = L.lddmm_comp_grid(N, prm, 0, 1.0)
+    P1 = L.lddmm_comp_grid(N, L.Params(T=2), 0, 1.0)
+    assert P1 != P2
+    for call in (lambda v: L.lddmm_energy(M, M, None, None, v, prm),
+                 lambda v: L.lddmm_gradient(M, M, None, None, v, prm)):
+        with pytest.raises(ValueError, match="v:"):
+            call(torch.zeros((2, 3) + P2))
+        with pytest.raises(ValueError, match="device tensor"):   # shape accepted
+            call(torch.zeros((2, 3) + P1))
