@@ -343,16 +343,22 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * [2, 32], then halved while columns x length exceeds 4096; defaults 16 and 8).
  * LDDMM_TUNE_STAGED_MIN_BLOCKS: the backward sweep uses its LDS-staged kernel
  * on grids that give at least this many blocks (one per 32 x 8 column and
- * z-slab; default 2048, at most 4096 blocks).  Sweep-block counts change
- * only the order of the FP64 energy partial sums.  A value applies to calls
- * enqueued after it is set.  Returns LDDMM_OK or LDDMM_EINVAL (unknown `which`
- * or value < 1).
+ * z-slab; default 2048, at most 4096 blocks).  LDDMM_TUNE_FWD_TILES: the
+ * forward sweep gives each thread a column of one xy plane block (256 voxels)
+ * and a run of consecutive z-planes, with about this many blocks (whole runs,
+ * a multiple of 8, at most 4096; default 2048), on grids whose xy plane needs
+ * at most 4089 such blocks; 0 selects the grid-stride forward sweep with
+ * LDDMM_TUNE_SWEEP_BLOCKS blocks on every grid.  Block counts and traversals
+ * change only the order of the FP64 energy partial sums.  A value applies to
+ * calls enqueued after it is set.  Returns LDDMM_OK or LDDMM_EINVAL (unknown
+ * `which`, or value < 1; value < 0 for LDDMM_TUNE_FWD_TILES).
  */
 #define LDDMM_TUNE_SWEEP_BLOCKS 0
 #define LDDMM_TUNE_FFT_X_ELEMS  1
 #define LDDMM_TUNE_FFT_COLS     2
 #define LDDMM_TUNE_FFT_ZCOLS    3
 #define LDDMM_TUNE_STAGED_MIN_BLOCKS 4
+#define LDDMM_TUNE_FWD_TILES    5
 int lddmm_set_tunable(int32_t which, int32_t value);
 
 /* Device copy of n floats, src -> dst (device, not overlapping): the library's

@@ -189,9 +189,16 @@ __device__ __forceinline__ Nbr periodic_nbr(const Geom& g, uint32_t i, int x, in
   return b;
 }
 
+// 7-point Laplacian (unit spacing) from the six neighbour values and the centre;
+// every caller goes through this one expression, so all give the same bits.
+__device__ __forceinline__ float lap7_of(float xm, float xp, float ym, float yp, float zm, float zp,
+                                         float center) {
+  return (xm + xp) + (ym + yp) + (zm + zp) - 6.f * center;
+}
+
 __device__ __forceinline__ float lap7_b(rsrc_t f, const Nbr& b, float center) {
-  return (bld(f, b.xm) + bld(f, b.xp)) + (bld(f, b.ym) + bld(f, b.yp)) +
-         (bld(f, b.zm) + bld(f, b.zp)) - 6.f * center;
+  return lap7_of(bld(f, b.xm), bld(f, b.xp), bld(f, b.ym), bld(f, b.yp), bld(f, b.zm),
+                 bld(f, b.zp), center);
 }
 
 // Trilinear sample of a field at a clamped cell (all 8 corners inside the grid).

@@ -128,76 +128,96 @@ __device__ __forceinline__ void rk4_mean(rsrc_t V0, rsrc_t V1, rsrc_t V2, const 
 
 // ---------------------------------------------------------- forward sweep ----
 
-template <int NC, bool FIRST, bool LAST, bool RK4 = false>
-__device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, uint32_t ntiles) {
-  const State* st = a.st;
-  if (st->mode == MODE_STOPPED) return;
-  const Geom g = a.g;
-  const long long N = g.n;
+// Buffers of forward step j as raw buffer descriptors.
+template <int NC>
+struct FwdView {
+  rsrc_t V0, V1, V2;            // v_j
+  rsrc_t U0, U1, U2;            // u0_j
+  rsrc_t W0, W1, W2;            // u0_{j+1}
+  rsrc_t T0[NC], T1[NC], OUT[NC];
+  rsrc_t IM0, IM1;              // monitored image channel
+};
+
+template <int NC, bool LAST>
+__device__ __forceinline__ FwdView<NC> fwd_view(const FwdArgs& a) {
+  const long long N = a.g.n;
   const uint32_t n = (uint32_t)N;
-  const float* vb = (st->eval ? a.vB : a.vA) + (long long)a.j * 3 * N;
-  const rsrc_t V0 = rsrc(vb, n), V1 = rsrc(vb + N, n), V2 = rsrc(vb + 2 * N, n);
-  const rsrc_t U0 = rsrc(a.u_cur, n), U1 = rsrc(a.u_cur + N, n), U2 = rsrc(a.u_cur + 2 * N, n);
-  const rsrc_t W0 = rsrc(a.u_next, n), W1 = rsrc(a.u_next + N, n), W2 = rsrc(a.u_next + 2 * N, n);
-  rsrc_t T0[NC], OUT[NC], T1[NC];
+  FwdView<NC> f;
+  const float* vb = (a.st->eval ? a.vB : a.vA) + (long long)a.j * 3 * N;
+  f.V0 = rsrc(vb, n);
+  f.V1 = rsrc(vb + N, n);
+  f.V2 = rsrc(vb + 2 * N, n);
+  f.U0 = rsrc(a.u_cur, n);
+  f.U1 = rsrc(a.u_cur + N, n);
+  f.U2 = rsrc(a.u_cur + 2 * N, n);
+  f.W0 = rsrc(a.u_next, n);
+  f.W1 = rsrc(a.u_next + N, n);
+  f.W2 = rsrc(a.u_next + 2 * N, n);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    T0[c] = rsrc(a.J0 + (long long)a.ch[c] * N, n);
-    T1[c] = rsrc(a.J1 + (long long)a.ch[c] * N, n);
-    OUT[c] = rsrc((LAST ? a.r : a.J0t_next) + (long long)c * N, n);
+    f.T0[c] = rsrc(a.J0 + (long long)a.ch[c] * N, n);
+    f.T1[c] = rsrc(a.J1 + (long long)a.ch[c] * N, n);
+    f.OUT[c] = rsrc((LAST ? a.r : a.J0t_next) + (long long)c * N, n);
   }
   const int ic = a.img_ch >= 0 ? a.img_ch : 0;
-  const rsrc_t IM0 = rsrc(a.J0 + (long long)ic * N, n), IM1 = rsrc(a.J1 + (long long)ic * N, n);
-  const bool mon = LAST && a.img_ch >= 0 && !a.img_weighted;
+  f.IM0 = rsrc(a.J0 + (long long)ic * N, n);
+  f.IM1 = rsrc(a.J1 + (long long)ic * N, n);
+  return f;
+}
+
+// Forward step j at voxel i = (x, y, z): the map step, the deformed templates
+// (the residual and the data terms at the last step) and the regulariser term
+// |gamma v - alpha Lap v|^2 from v_j = (vx, vy, vz) and its 7-point Laplacians.
+template <int NC, bool FIRST, bool LAST, bool RK4>
+__device__ __forceinline__ void forward_voxel(const FwdArgs& a, const FwdView<NC>& f, uint32_t i,
+                                              int x, int y, int z, float vx, float vy, float vz,
+                                              float lapx, float lapy, float lapz, double& accR,
+                                              double& accD, double& accI) {
+  const Geom& g = a.g;
   const float dt = a.dt, ih = g.inv_h;
   const float c2 = a.alpha * ih * ih;
-  double accR = 0.0, accD = 0.0, accI = 0.0;
-  const XcdRange rg = xcd_range(n, tile, ntiles);
-  for (uint32_t i = rg.first; i < rg.end; i += rg.stride) {
-    int x, y, z;
-    vcoord(g, i, x, y, z);
-    const float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
-    float mx = vx, my = vy, mz = vz;                    // velocity of the map step
-    if (RK4) rk4_mean(V0, V1, V2, g, x, y, z, -dt * ih, mx, my, mz);
-    float ux = -dt * mx, uy = -dt * my, uz = -dt * mz;
-    if (!FIRST) {
-      const Cell cl = make_cell_clamp(g, x, y, z, -dt * mx * ih, -dt * my * ih, -dt * mz * ih);
-      ux += sample(U0, cl);
-      uy += sample(U1, cl);
-      uz += sample(U2, cl);
-    }
-    bst(W0, i, ux);
-    bst(W1, i, uy);
-    bst(W2, i, uz);
-    // deformed templates at t_{j+1}
-    {
-      const Cell cz = make_cell_zero(g, x, y, z, ux * ih, uy * ih, uz * ih);
+  float mx = vx, my = vy, mz = vz;                    // velocity of the map step
+  if (RK4) rk4_mean(f.V0, f.V1, f.V2, g, x, y, z, -dt * ih, mx, my, mz);
+  float ux = -dt * mx, uy = -dt * my, uz = -dt * mz;
+  if (!FIRST) {
+    const Cell cl = make_cell_clamp(g, x, y, z, -dt * mx * ih, -dt * my * ih, -dt * mz * ih);
+    ux += sample(f.U0, cl);
+    uy += sample(f.U1, cl);
+    uz += sample(f.U2, cl);
+  }
+  bst(f.W0, i, ux);
+  bst(f.W1, i, uy);
+  bst(f.W2, i, uz);
+  // deformed templates at t_{j+1}
+  {
+    const Cell cz = make_cell_zero(g, x, y, z, ux * ih, uy * ih, uz * ih);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const float val = sample(T0[c], cz);
-        if (!LAST) {
-          bst(OUT[c], i, val);
-        } else {
-          const float r = val - bld(T1[c], i);
-          bst(OUT[c], i, r);
-          accD += (double)a.w[c] * (double)r * (double)r;
-          if (a.img_weighted && c == a.img_slot) accI += (double)r * (double)r;
-        }
-      }
-      if (mon) {
-        const float d = sample(IM0, cz) - bld(IM1, i);
-        accI += (double)d * (double)d;
+    for (int c = 0; c < NC; ++c) {
+      const float val = sample(f.T0[c], cz);
+      if (!LAST) {
+        bst(f.OUT[c], i, val);
+      } else {
+        const float r = val - bld(f.T1[c], i);
+        bst(f.OUT[c], i, r);
+        accD += (double)a.w[c] * (double)r * (double)r;
+        if (a.img_weighted && c == a.img_slot) accI += (double)r * (double)r;
       }
     }
-    // |L v_j|^2 with L = gamma - alpha Lap (periodic 7-point)
-    {
-      const Nbr nb = periodic_nbr(g, i, x, y, z);
-      const float lx = a.gamma * vx - c2 * lap7_b(V0, nb, vx);
-      const float ly = a.gamma * vy - c2 * lap7_b(V1, nb, vy);
-      const float lz = a.gamma * vz - c2 * lap7_b(V2, nb, vz);
-      accR += (double)lx * lx + (double)ly * ly + (double)lz * lz;
+    if (LAST && a.img_ch >= 0 && !a.img_weighted) {
+      const float d = sample(f.IM0, cz) - bld(f.IM1, i);
+      accI += (double)d * (double)d;
     }
   }
+  // |L v_j|^2 with L = gamma - alpha Lap (periodic 7-point)
+  const float lx = a.gamma * vx - c2 * lapx;
+  const float ly = a.gamma * vy - c2 * lapy;
+  const float lz = a.gamma * vz - c2 * lapz;
+  accR += (double)lx * lx + (double)ly * ly + (double)lz * lz;
+}
+
+template <bool LAST>
+__device__ __forceinline__ void forward_partials(const FwdArgs& a, uint32_t tile, double accR,
+                                                 double accD, double accI) {
   const double sR = block_sum(accR);
   if (threadIdx.x == 0) a.partR[tile] = sR;
   if (LAST) {
@@ -210,9 +230,104 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, ui
   }
 }
 
-template <int NC, bool FIRST, bool LAST, bool RK4>
+// Grid-stride traversal: the XCD slabs of xcd_range, every voxel on its own.
+template <int NC, bool FIRST, bool LAST, bool RK4 = false>
+__device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, uint32_t ntiles) {
+  if (a.st->mode == MODE_STOPPED) return;
+  const Geom g = a.g;
+  const FwdView<NC> f = fwd_view<NC, LAST>(a);
+  double accR = 0.0, accD = 0.0, accI = 0.0;
+  const XcdRange rg = xcd_range((uint32_t)g.n, tile, ntiles);
+  for (uint32_t i = rg.first; i < rg.end; i += rg.stride) {
+    int x, y, z;
+    vcoord(g, i, x, y, z);
+    const float vx = bld(f.V0, i), vy = bld(f.V1, i), vz = bld(f.V2, i);
+    const Nbr nb = periodic_nbr(g, i, x, y, z);
+    forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vx, vy, vz, lap7_b(f.V0, nb, vx),
+                                        lap7_b(f.V1, nb, vy), lap7_b(f.V2, nb, vz), accR, accD,
+                                        accI);
+  }
+  forward_partials<LAST>(a, tile, accR, accD, accI);
+}
+
+// Plane-marching traversal.  A tile is kBlock consecutive voxels of an xy plane
+// over a run of consecutive planes; each thread walks its column up the run and
+// keeps v_j of the planes below, at and above the current one in registers (the
+// z terms of the stencil), loading the plane after next one step ahead, so the
+// gathers of a step never wait on the load of v.  Tiles go to the XCDs in
+// contiguous runs (block b runs on XCD b mod 8), so the rows above and below a
+// tile, which the stencil and the gathers read, come from neighbouring tiles of
+// the same XCD and its L2.  ntiles is a multiple of 8 and at least the number of
+// plane blocks ceil(nx ny / kBlock); tiles past the last run are idle.
+template <int NC, bool FIRST, bool LAST, bool RK4 = false>
+__device__ __forceinline__ void forward_zmarch_body(const FwdArgs& a, uint32_t tile,
+                                                    uint32_t ntiles) {
+  if (a.st->mode == MODE_STOPPED) return;
+  const Geom g = a.g;
+  const FwdView<NC> f = fwd_view<NC, LAST>(a);
+  const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;
+  const uint32_t nxy = nx * ny;
+  const uint32_t nb = (nxy + kBlock - 1) / kBlock;
+  uint32_t nzc = ntiles / nb;
+  nzc = nzc < 1 ? 1 : (nzc > nz ? nz : nzc);
+  const uint32_t run = (nz + nzc - 1) / nzc;
+  const uint32_t l = (tile % kXCD) * (ntiles / kXCD) + tile / kXCD;
+  const uint32_t zc = l / nb;
+  const uint32_t p = (l - zc * nb) * kBlock + threadIdx.x;   // index within the plane
+  const uint32_t z0 = zc * run;
+  double accR = 0.0, accD = 0.0, accI = 0.0;
+  if (p < nxy && z0 < nz) {
+    const uint32_t z1 = z0 + run < nz ? z0 + run : nz;
+    const uint32_t yq = fdiv(p, g.fx);
+    const int x = (int)(p - yq * nx), y = (int)yq;
+    // periodic in-plane neighbours as offsets added to i (modulo 2^32)
+    const uint32_t dxm = x == 0 ? nx - 1 : 0u - 1u;
+    const uint32_t dxp = x == (int)nx - 1 ? 0u - (nx - 1) : 1u;
+    const uint32_t dym = y == 0 ? (ny - 1) * nx : 0u - nx;
+    const uint32_t dyp = y == (int)ny - 1 ? 0u - (ny - 1) * nx : nx;
+    const rsrc_t V[3] = {f.V0, f.V1, f.V2};
+    const uint32_t zb = z0 == 0 ? nz - 1 : z0 - 1;
+    uint32_t zp = z0 + 1 == nz ? 0 : z0 + 1;
+    float vm[3], vc[3], vp[3];                               // v_j at z - 1, z, z + 1
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vm[c] = bld(V[c], zb * nxy + p);
+      vc[c] = bld(V[c], z0 * nxy + p);
+      vp[c] = bld(V[c], zp * nxy + p);
+    }
+    for (uint32_t z = z0; z < z1; ++z) {
+      const uint32_t i = z * nxy + p;
+      const uint32_t zn = zp + 1 == nz ? 0 : zp + 1;         // the plane after next
+      float vn[3] = {0.f, 0.f, 0.f};
+      if (z + 1 < z1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vn[c] = bld(V[c], zn * nxy + p);
+      }
+      float lap[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        lap[c] = lap7_of(bld(V[c], i + dxm), bld(V[c], i + dxp), bld(V[c], i + dym),
+                         bld(V[c], i + dyp), vm[c], vp[c], vc[c]);
+      forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, (int)z, vc[0], vc[1], vc[2], lap[0],
+                                          lap[1], lap[2], accR, accD, accI);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        vm[c] = vc[c];
+        vc[c] = vp[c];
+        vp[c] = vn[c];
+      }
+      zp = zn;
+    }
+  }
+  forward_partials<LAST>(a, tile, accR, accD, accI);
+}
+
+template <int NC, bool FIRST, bool LAST, bool RK4, bool ZM>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
-  forward_body<NC, FIRST, LAST, RK4>(a, blockIdx.x, gridDim.x);
+  if (ZM)
+    forward_zmarch_body<NC, FIRST, LAST, RK4>(a, blockIdx.x, gridDim.x);
+  else
+    forward_body<NC, FIRST, LAST, RK4>(a, blockIdx.x, gridDim.x);
 }
 
 // One launch for every problem of a batch: block b runs tile b - off[p] of problem p.
@@ -220,21 +335,54 @@ template <int NC, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) {
   const int p = batch_pair(br, blockIdx.x);
   const PairTab* t = (const PairTab*)br.tab[p];
-  forward_body<NC, FIRST, LAST>(t->fwd[j], blockIdx.x - br.off[p], br.off[p + 1] - br.off[p]);
+  const uint32_t tile = blockIdx.x - br.off[p], ntiles = br.off[p + 1] - br.off[p];
+  if (t->fwd[j].zmarch)
+    forward_zmarch_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
+  else
+    forward_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
+}
+
+// Tiles of a plane-marching launch (a multiple of 8 near g_fwd_tiles, at least
+// the plane blocks); 0 selects the grid-stride traversal.
+static int g_fwd_tiles = 2048;
+
+void set_fwd_tiles(int t) { g_fwd_tiles = t <= 0 ? 0 : (t > kPartMax ? kPartMax : t); }
+
+static long long plane_blocks(const Geom& g) {
+  return ((long long)g.nx * g.ny + kBlock - 1) / kBlock;
+}
+
+bool forward_zmarch(const Geom& g) {
+  return g_fwd_tiles > 0 && plane_blocks(g) <= kPartMax - (kXCD - 1);
+}
+
+int forward_tiles(const Geom& g) {
+  if (!forward_zmarch(g)) return reduce_grid(g.n);
+  const long long nb = plane_blocks(g);
+  long long nzc = (g_fwd_tiles + nb - 1) / nb;                // runs of planes
+  const long long cap = (kPartMax - (kXCD - 1)) / nb;         // so that the tiles fit kPartMax
+  if (nzc > cap) nzc = cap;
+  if (nzc > g.nz) nzc = g.nz;
+  if (nzc < 1) nzc = 1;
+  const long long run = (g.nz + nzc - 1) / nzc;
+  nzc = (g.nz + run - 1) / run;
+  return (int)((nb * nzc + kXCD - 1) / kXCD * kXCD);
 }
 
 template <int NC, bool RK4>
 static void fwd_dispatch(const FwdArgs& a, hipStream_t s) {
-  const int grid = reduce_grid(a.g.n);
+  const int grid = a.zmarch ? forward_tiles(a.g) : reduce_grid(a.g.n);
   const bool first = (a.j == 0), last = (a.j == a.T - 1);
-  if (first && last)
-    hipLaunchKernelGGL((k_forward<NC, true, true, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
-  else if (first)
-    hipLaunchKernelGGL((k_forward<NC, true, false, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
-  else if (last)
-    hipLaunchKernelGGL((k_forward<NC, false, true, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_forward<NC, false, false, RK4>), dim3(grid), dim3(kBlock), 0, s, a);
+#define FWD(F, L, Z) \
+  hipLaunchKernelGGL((k_forward<NC, F, L, RK4, Z>), dim3(grid), dim3(kBlock), 0, s, a)
+  if (a.zmarch) {
+    if (first && last) FWD(true, true, true); else if (first) FWD(true, false, true);
+    else if (last) FWD(false, true, true); else FWD(false, false, true);
+  } else {
+    if (first && last) FWD(true, true, false); else if (first) FWD(true, false, false);
+    else if (last) FWD(false, true, false); else FWD(false, false, false);
+  }
+#undef FWD
 }
 
 

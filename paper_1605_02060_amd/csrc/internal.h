@@ -110,6 +110,7 @@ struct FwdArgs {
   double* partI;          // [kPartMax]
   const State* st;
   int rk4;                // departure points by fourth-order Runge-Kutta
+  int zmarch;             // plane-marching traversal (forward_tiles blocks), else grid-stride
 };
 
 struct BwdArgs {
@@ -227,9 +228,14 @@ void set_sweep_blocks(int blocks);
 void set_fft_x_elems(int elems);
 void set_fft_cols(int axis, int cols);   // axis 0: y tiles, 1: z tiles
 void launch_forward(const FwdArgs& a, hipStream_t s);
+// Forward sweep traversal on grid g and its blocks (= the partials it writes),
+// single or batched; set_fwd_tiles(0) selects the grid-stride sweep.
+void set_fwd_tiles(int tiles);
+bool forward_zmarch(const Geom& g);
+int forward_tiles(const Geom& g);
 void launch_backward(const BwdArgs& a, hipStream_t s);
 // Blocks of a body-force launch of the backward sweep on this grid = the min-det
-// partials it writes (single or batched).  Forward launches use reduce_grid.
+// partials it writes (single or batched).
 int backward_partials(const Geom& g);
 bool backward_staged(const Geom& g);
 void set_staged_min_blocks(int blocks);

@@ -351,6 +351,7 @@ static void forward_steps(Ctx& c, int li, const float* vA, const float* vB, cons
     a.partI = c.partI;
     a.st = c.st;
     a.rk4 = k.rk4;
+    a.zmarch = forward_zmarch(L.g);
     ProfScope ps(LDDMM_PROF_FORWARD, n, s);
     launch_forward(a, s);
   }
@@ -550,7 +551,7 @@ static void exact_gradient(Ctx& c, const float* v, float* grad, hipStream_t s) {
 
 static void decide(Ctx& c, int li, int init, double* trace, hipStream_t s) {
   const Level& L = c.cfg.lv[li];
-  const int nb = reduce_grid(L.g.n);
+  const int nb = forward_tiles(L.g);
   const int nbw = backward_partials(L.g);
   const double h = (double)L.g.h;
   ProfScope ps(LDDMM_PROF_OTHER, 0, s);
@@ -785,6 +786,7 @@ static void build_pairtab(Ctx& c, int li, PairTab* t) {
     a.partD = c.partD;
     a.partI = c.partI;
     a.st = c.st;
+    a.zmarch = forward_zmarch(L.g);
   }
   for (int j = k.T - 1; j >= -1; --j) {
     BwdArgs& a = t->bwd[j + 1];
@@ -828,7 +830,7 @@ static void build_pairtab(Ctx& c, int li, PairTab* t) {
   }
   FftLaunch Lf;
   t->fft = make_fft(c, li, MODE_GRAD, &Lf);
-  const int nb = reduce_grid(n);
+  const int nb = forward_tiles(L.g);
   const int nbw = backward_partials(L.g);
   const double h = (double)L.g.h;
   for (int init = 0; init < 2; ++init) {
@@ -925,7 +927,7 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
       FftLaunch Lf;
       FftPair tmp = make_fft(c, li, MODE_GRAD, &Lf);
       (void)tmp;
-      tf[p] = reduce_grid(lv.g.n);
+      tf[p] = forward_tiles(lv.g);
       tb[p] = backward_partials(lv.g);
       tx[p] = Lf.x_tiles;
       ty[p] = Lf.y_tiles;
@@ -1159,6 +1161,11 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
   if (which == LDDMM_TUNE_SWEEP_BLOCKS) {
     if (value < 1) return LDDMM_EINVAL;
     set_sweep_blocks(value);
+    return LDDMM_OK;
+  }
+  if (which == LDDMM_TUNE_FWD_TILES) {
+    if (value < 0) return LDDMM_EINVAL;
+    set_fwd_tiles(value);
     return LDDMM_OK;
   }
   if (which == LDDMM_TUNE_STAGED_MIN_BLOCKS) {

@@ -1,8 +1,9 @@
 """Launch-shape autotuner for the registration kernels.
 
-The library exposes three process-wide launch-shape tunables (sweep blocks,
-x-pass LDS budget, y/z tile columns); none of them changes a result, only the
-speed.  `autotune` times a short fixed-step registration of the caller's own
+The library exposes process-wide launch-shape tunables (sweep blocks, the
+forward sweep's plane-marching tiles, the backward sweep's staged threshold,
+the x-pass LDS budget, the y / z tile columns); none of them changes a result
+beyond the order of the FP64 energy sums, only the speed.  `autotune` times a short fixed-step registration of the caller's own
 problems (their pyramid, a few iterations per level) for each candidate value, one tunable at a time (coordinate search from
 the defaults), keeps the fastest, and caches the choice in a JSON file keyed by
 architecture, T and the computational grids.  `apply` sets a cached choice.
@@ -18,16 +19,18 @@ import torch
 
 from . import lddmm as L
 
-DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 1024, L.TUNE_STAGED_MIN_BLOCKS: 2048, L.TUNE_FFT_X_ELEMS: 2048,
-            L.TUNE_FFT_COLS: 16, L.TUNE_FFT_ZCOLS: 8}
+DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 1024, L.TUNE_FWD_TILES: 2048, L.TUNE_STAGED_MIN_BLOCKS: 2048,
+            L.TUNE_FFT_X_ELEMS: 2048, L.TUNE_FFT_COLS: 16, L.TUNE_FFT_ZCOLS: 8}
 CANDIDATES = {
     L.TUNE_SWEEP_BLOCKS: (512, 1024, 2048, 4096),
+    L.TUNE_FWD_TILES: (0, 1024, 2048, 4096),
     L.TUNE_STAGED_MIN_BLOCKS: (1, 1024, 2048, 1 << 30),
     L.TUNE_FFT_X_ELEMS: (1024, 2048, 4096),
     L.TUNE_FFT_COLS: (4, 8, 16, 32),
     L.TUNE_FFT_ZCOLS: (4, 8, 16, 32),
 }
-NAMES = {L.TUNE_SWEEP_BLOCKS: "sweep_blocks", L.TUNE_STAGED_MIN_BLOCKS: "staged_min_blocks",
+NAMES = {L.TUNE_SWEEP_BLOCKS: "sweep_blocks", L.TUNE_FWD_TILES: "fwd_tiles",
+         L.TUNE_STAGED_MIN_BLOCKS: "staged_min_blocks",
          L.TUNE_FFT_X_ELEMS: "fft_x_elems",
          L.TUNE_FFT_COLS: "fft_cols", L.TUNE_FFT_ZCOLS: "fft_zcols"}
 
