@@ -279,24 +279,36 @@ def compute_traffic(fetch_db, write_db, out_path):
         factors[tag] = 4.0 * COPY_FLOATS / (1024.0 * sum(copy) / len(copy))
         per[tag] = rows
     out["fetch_factor"], out["write_factor"] = factors["fetch"], factors["write"]
-    # finest-level dispatches of each class: the longest launch-shape group per variant
+    # finest-level dispatches of each class.  A launch-shape group (split where
+    # one shape runs at two pyramid levels) is at the finest level when its mean
+    # counter value is at least 0.3 of the class's largest: levels differ 8x in
+    # voxels, the kernel variants of a class (first step, map-only steps) at most
+    # about 2x in bytes per voxel, so the coarser levels fall below and a variant
+    # that never runs on the finest grid drops out.  Of a variant's finest-level
+    # groups the one with the most dispatches is taken (the timed steps, not the
+    # autotuner's trials of other shapes).  Grids alone do not tell the levels
+    # apart: plane-marching launches size their grid by planes and runs, so a
+    # coarser level can launch more blocks.
     classes = {"forward": r"^void k_forward<", "backward": r"^void k_backward(_staged)?<"}
     for cls, pat in classes.items():
         tot = {"fetch": [], "write": []}
         durs = []
         for tag in ("fetch", "write"):
-            for (name, grid), items in per[tag].items():
-                if not re.match(pat, name):
+            parts = [(name, part) for (name, grid), items in per[tag].items()
+                     if re.match(pat, name)
+                     for sub, part in _split_levels([(d, v) for d, v in items])]
+            if not parts:
+                continue
+            mean_v = [sum(v for d, v in part) / len(part) for name, part in parts]
+            top = max(mean_v)
+            for name in sorted({name for name, part in parts}):
+                cand = [part for (n2, part), m in zip(parts, mean_v) if n2 == name and m >= 0.3 * top]
+                if not cand:
                     continue
-                for sub, part in _split_levels([(d, v) for d, v in items]):
-                    if sub == " (short)":
-                        continue
-                    if len({g for (n2, g) in per[tag] if n2 == name}) > 1 and grid != max(
-                            g for (n2, g) in per[tag] if n2 == name):
-                        continue
-                    tot[tag] += [v * 1024.0 * factors[tag] for d, v in part]
-                    if tag == "fetch":
-                        durs += [d for d, v in part]
+                part = max(cand, key=len)
+                tot[tag] += [v * 1024.0 * factors[tag] for d, v in part]
+                if tag == "fetch":
+                    durs += [d for d, v in part]
         if tot["fetch"] and tot["write"]:
             f = sum(tot["fetch"]) / len(tot["fetch"])
             w = sum(tot["write"]) / len(tot["write"])
@@ -769,6 +781,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="run the workload's autotuning (filling the tune cache) and exit, so "
+                         "that profiled runs after it contain no trial launches")
     ap.add_argument("--trace-out", default=None)
     ap.add_argument("--workload", choices=("atlas", "atlas-rk4", "batched", "histmatch", "align",
                                            "masks"),
@@ -837,6 +852,8 @@ def main():
                            prm, verbose=False)
     tunables = {tune.NAMES[w]: v for w, v in choice.items()}
     log(f"autotune {time.perf_counter() - t_tune:.1f} s: {tunables}")
+    if args.tune_only:
+        return
     v = torch.zeros((T, 3) + P, dtype=torch.float32, device=dev)
     units = work_units(pair.shape)
 

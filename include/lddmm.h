@@ -345,8 +345,9 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * on grids that give at least this many blocks (one per 32 x 8 column and
  * z-slab; default 2048, at most 4096 blocks).  LDDMM_TUNE_FWD_TILES: the
  * forward sweep gives each thread a column of one xy plane block (256 voxels)
- * and a run of consecutive z-planes, with about this many blocks (whole runs,
- * a multiple of 8, at most 4096; default 2048), on grids whose xy plane needs
+ * and a run of consecutive z-planes, with at most this many blocks where that
+ * allows one run per plane block (whole runs, rounded up to a multiple of 8, at
+ * most 4096; default 3584), on grids whose xy plane needs
  * at most 4089 such blocks; 0 selects the grid-stride forward sweep with
  * LDDMM_TUNE_SWEEP_BLOCKS blocks on every grid.  Block counts and traversals
  * change only the order of the FP64 energy partial sums.  A value applies to

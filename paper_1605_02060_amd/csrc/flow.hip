@@ -342,9 +342,10 @@ __global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) 
     forward_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
 }
 
-// Tiles of a plane-marching launch (a multiple of 8 near g_fwd_tiles, at least
-// the plane blocks); 0 selects the grid-stride traversal.
-static int g_fwd_tiles = 2048;
+// Tiles of a plane-marching launch: whole runs of planes for every plane block,
+// at most g_fwd_tiles where that allows one run, rounded up to a multiple of 8;
+// 0 selects the grid-stride traversal.
+static int g_fwd_tiles = 3584;
 
 void set_fwd_tiles(int t) { g_fwd_tiles = t <= 0 ? 0 : (t > kPartMax ? kPartMax : t); }
 
@@ -359,7 +360,7 @@ bool forward_zmarch(const Geom& g) {
 int forward_tiles(const Geom& g) {
   if (!forward_zmarch(g)) return reduce_grid(g.n);
   const long long nb = plane_blocks(g);
-  long long nzc = (g_fwd_tiles + nb - 1) / nb;                // runs of planes
+  long long nzc = g_fwd_tiles / nb;                           // runs of planes
   const long long cap = (kPartMax - (kXCD - 1)) / nb;         // so that the tiles fit kPartMax
   if (nzc > cap) nzc = cap;
   if (nzc > g.nz) nzc = g.nz;

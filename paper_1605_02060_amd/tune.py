@@ -19,11 +19,11 @@ import torch
 
 from . import lddmm as L
 
-DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 1024, L.TUNE_FWD_TILES: 2048, L.TUNE_STAGED_MIN_BLOCKS: 2048,
+DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 1024, L.TUNE_FWD_TILES: 3584, L.TUNE_STAGED_MIN_BLOCKS: 2048,
             L.TUNE_FFT_X_ELEMS: 2048, L.TUNE_FFT_COLS: 16, L.TUNE_FFT_ZCOLS: 8}
 CANDIDATES = {
     L.TUNE_SWEEP_BLOCKS: (512, 1024, 2048, 4096),
-    L.TUNE_FWD_TILES: (0, 1024, 2048, 4096),
+    L.TUNE_FWD_TILES: (0, 1792, 2048, 3584, 4096),
     L.TUNE_STAGED_MIN_BLOCKS: (1, 1024, 2048, 1 << 30),
     L.TUNE_FFT_X_ELEMS: (1024, 2048, 4096),
     L.TUNE_FFT_COLS: (4, 8, 16, 32),

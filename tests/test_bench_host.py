@@ -38,9 +38,21 @@ def _rows(copy_kib, fwd_kib, bwd_kib):
               fwd_kib)] * 4
     rows += [("void lddmm::k_forward<1, false, false, false>(lddmm::FwdArgs)", 262144, 26000,
               fwd_kib / 8)] * 4
-    # staged backward at the finest level only
+    # plane-marching forward: the finest level (long), a coarser level whose grid
+    # is larger (short), and two trial launches of another shape at the finest level
+    zm = "void lddmm::k_forward<1, false, false, false, true>(lddmm::FwdArgs)"
+    rows += [(zm, 448512, 187000, fwd_kib)] * 5
+    rows += [(zm, 450560, 22000, fwd_kib / 8)] * 6
+    rows += [(zm, 897024, 185000, 1.5 * fwd_kib)] * 2
+    # staged backward at the finest level only; a map-only step at the finest level
+    # (60 % of the bytes); a grid-stride body-force variant that runs only on a
+    # coarser level (left out)
     rows += [("void lddmm::k_backward_staged<1, true, false>(lddmm::BwdArgs)", 737280, 205000,
               bwd_kib)] * 4
+    rows += [("void lddmm::k_backward<1, true, true, false, false>(lddmm::BwdArgs)", 262144,
+              41000, 0.6 * bwd_kib)] * 2
+    rows += [("void lddmm::k_backward<1, true, false, true, false>(lddmm::BwdArgs)", 262144,
+              29000, bwd_kib / 8)] * 6
     return rows
 
 
@@ -59,12 +71,14 @@ def test_traffic_is_calibrated_on_the_finest_copies(tmp_path):
     assert t["fetch_factor"] == pytest.approx(2.0) and t["write_factor"] == pytest.approx(1.0)
     assert t["source_sha"] == bench.library_sources_sha()
     k = t["kernels"]
-    assert k["forward"]["launches"] == 4                      # the coarse launches left out
+    # the coarse launches and the trial shape left out: 4 grid-stride + 5 marching
+    assert k["forward"]["launches"] == 9
     assert k["forward"]["fetch_bytes_per_voxel"] == pytest.approx(61.0)
     assert k["forward"]["write_bytes_per_voxel"] == pytest.approx(16.0)
-    assert k["backward"]["fetch_bytes_per_voxel"] == pytest.approx(50.0)
-    assert k["backward"]["write_bytes_per_voxel"] == pytest.approx(30.0)
-    assert k["forward"]["mean_us_under_counters"] == pytest.approx(206.0)
+    assert k["backward"]["launches"] == 6
+    assert k["backward"]["fetch_bytes_per_voxel"] == pytest.approx((4 * 50.0 + 2 * 30.0) / 6)
+    assert k["backward"]["write_bytes_per_voxel"] == pytest.approx((4 * 30.0 + 2 * 18.0) / 6)
+    assert k["forward"]["mean_us_under_counters"] == pytest.approx((4 * 206.0 + 5 * 187.0) / 9)
 
 
 def test_missing_copy_is_an_error(tmp_path):
@@ -81,6 +95,8 @@ def test_summary_names_and_levels(tmp_path):
     names = {k[0] for k in out}
     assert "void k_forward<1, false, false, false>" in names      # namespaces and args dropped
     assert "k_copy" in names
-    tags = {k[2] for k in out if k[0].startswith("void k_forward")}
+    tags = {k[2] for k in out if k[0] == "void k_forward<1, false, false, false>"}
     assert tags == {" (short)", " (long)"}                         # two levels split
+    tags = {k[2] for k in out if k[0] == "void k_forward<1, false, false, false, true>"}
+    assert tags == {""}                                            # one level per shape
     assert open(tmp_path / "s.txt").readline().startswith("# rocprofv3 summary of: cmd")
