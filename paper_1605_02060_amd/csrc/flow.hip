@@ -562,35 +562,46 @@ __device__ __forceinline__ SlabTile slab_tile(const Geom& g, int block) {
 
 
 // Ring of map planes (3 components, halo kBH, clamped) staged through registers.
+// Slot-major layout: element e of a staged plane (component, window row, window
+// column: the order in which the block's threads load them) sits at s[slot] + e.
+// A thread's LDS addresses and in-plane global offsets are then the same on every
+// plane of the march and are computed once, before it.
 struct MapRing {
-  float (*s)[kBRing][kBYH][kBXH];
+  float (*s)[3][kBYH][kBXH];     // [slot][component][row][column]
   float reg[kURegs];
-  __device__ __forceinline__ void fetch(rsrc_t U, uint32_t n, const Geom& g, int x0, int y0, int p) {
+  uint32_t off[kURegs];          // in-plane element offset of element r, component included
+  uint32_t ok;                   // bit r: element r lies in the grid's (x, y) range
+  __device__ __forceinline__ void init(const Geom& g, uint32_t n, int x0, int y0) {
+    ok = 0u;
 #pragma unroll
     for (int r = 0; r < kURegs; ++r) {
       const int e = threadIdx.x + r * kBlock;
-      float val = 0.f;
-      if (e < kUPlane && p >= 0 && p < g.nz) {
-        const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
-        const int ly = rem / kBXH, lx = rem - ly * kBXH;
-        const int gx = x0 - kBH + lx, gy = y0 - kBH + ly;
-        if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny)
-          val = bld(U, (uint32_t)c * n + (uint32_t)((p * g.ny + gy) * g.nx + gx));
-      }
-      reg[r] = val;
-    }
-  }
-  __device__ __forceinline__ void put(int p) {
-    if (p < 0) return;
-    const int slot = p % kBRing;
-#pragma unroll
-    for (int r = 0; r < kURegs; ++r) {
-      const int e = threadIdx.x + r * kBlock;
+      off[r] = 0u;
       if (e < kUPlane) {
         const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
         const int ly = rem / kBXH, lx = rem - ly * kBXH;
-        s[c][slot][ly][lx] = reg[r];
+        const int gx = x0 - kBH + lx, gy = y0 - kBH + ly;
+        if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny) {
+          off[r] = (uint32_t)c * n + (uint32_t)(gy * g.nx + gx);
+          ok |= 1u << r;
+        }
       }
+    }
+  }
+  // Plane p into registers (0 outside the grid).
+  __device__ __forceinline__ void fetch(rsrc_t U, const Geom& g, int p) {
+    const bool pin = p >= 0 && p < g.nz;
+    const uint32_t po = pin ? (uint32_t)p * (uint32_t)(g.nx * g.ny) : 0u;
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) reg[r] = (pin && ((ok >> r) & 1u)) ? bld(U, off[r] + po) : 0.f;
+  }
+  __device__ __forceinline__ void put(int p) {
+    if (p < 0) return;
+    float* base = &s[p % kBRing][0][0][0];
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e < kUPlane) base[e] = reg[r];
     }
   }
   // Trilinear sample of all three components at the clamped cell (cx, cy, cz),
@@ -604,52 +615,60 @@ struct MapRing {
     const int za = cz % kBRing, zb = (cz + 1) % kBRing;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      out[c] = lerp8(s[c][za][wy][wx], s[c][za][wy][wx + 1], s[c][za][wy + 1][wx],
-                     s[c][za][wy + 1][wx + 1], s[c][zb][wy][wx], s[c][zb][wy][wx + 1],
-                     s[c][zb][wy + 1][wx], s[c][zb][wy + 1][wx + 1], fx, fy, fz);
+      out[c] = lerp8(s[za][c][wy][wx], s[za][c][wy][wx + 1], s[za][c][wy + 1][wx],
+                     s[za][c][wy + 1][wx + 1], s[zb][c][wy][wx], s[zb][c][wy][wx + 1],
+                     s[zb][c][wy + 1][wx], s[zb][c][wy + 1][wx + 1], fx, fy, fz);
     return true;
   }
 };
 
-// Ring of K-component planes z - 1 .. z + 1 with halo 1 (zero outside the grid).
+// Ring of K-component planes z - 1 .. z + 1 with halo 1 (zero outside the grid),
+// slot-major like MapRing.
 template <int K>
 struct HaloRing {
   static constexpr int kPlane = K * kBYJ * kBXJ;
   static constexpr int kRegs = (kPlane + kBlock - 1) / kBlock;
-  float (*s)[3][kBYJ][kBXJ];
+  float (*s)[K][kBYJ][kBXJ];     // [slot][component][row][column]
   float reg[kRegs];
-  // component c of plane p lives at base[c] (element offsets in one descriptor)
-  __device__ __forceinline__ void fetch(const rsrc_t* R, uint32_t n, const Geom& g, int x0,
-                                        int y0, int p) {
-    const int pw = p;
+  uint32_t off[kRegs];           // in-plane element offset of element r
+  uint32_t ok, c1;               // bit r: in the grid's (x, y) range / of component 1
+  __device__ __forceinline__ void init(const Geom& g, int x0, int y0) {
+    ok = 0u;
+    c1 = 0u;
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
       const int e = threadIdx.x + r * kBlock;
-      float val = 0.f;
-      if (e < kPlane && pw >= 0 && pw < g.nz) {
+      off[r] = 0u;
+      if (e < kPlane) {
         const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
         const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
         const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
         if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny) {
-          const uint32_t o = (uint32_t)((pw * g.ny + gy) * g.nx + gx);
-          val = bld(R[c < K ? c : K - 1], o);
+          off[r] = (uint32_t)(gy * g.nx + gx);
+          ok |= 1u << r;
+          if (c > 0) c1 |= 1u << r;
         }
       }
+    }
+  }
+  // Plane p of every component into registers; component c is read through R[c].
+  __device__ __forceinline__ void fetch(const rsrc_t* R, const Geom& g, int p) {
+    const bool pin = p >= 0 && p < g.nz;
+    const uint32_t po = pin ? (uint32_t)p * (uint32_t)(g.nx * g.ny) : 0u;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+      float val = 0.f;
+      if (pin && ((ok >> r) & 1u)) val = bld(R[K > 1 && ((c1 >> r) & 1u) ? 1 : 0], off[r] + po);
       reg[r] = val;
     }
-    (void)n;
   }
   __device__ __forceinline__ void put(int p) {
     if (p < 0) return;
-    const int slot = p % 3;
+    float* base = &s[p % 3][0][0][0];
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
       const int e = threadIdx.x + r * kBlock;
-      if (e < kPlane) {
-        const int c = e / (kBYJ * kBXJ), rem = e - c * (kBYJ * kBXJ);
-        const int ly = rem / kBXJ, lx = rem - ly * kBXJ;
-        s[c][slot][ly][lx] = reg[r];
-      }
+      if (e < kPlane) base[e] = reg[r];
     }
   }
 };
@@ -664,8 +683,8 @@ __device__ __forceinline__ float dstencil_v(float plus, float minus, float cente
 
 template <int NC, bool HAS_U, bool RK4 = false>
 __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block) {
-  __shared__ float su[3][kBRing][kBYH][kBXH];
-  __shared__ float sj[NC][3][kBYJ][kBXJ];
+  __shared__ float su[kBRing][3][kBYH][kBXH];
+  __shared__ float sj[3][NC][kBYJ][kBXJ];
   const State* st = a.st;
   if (a.need_mode >= 0 && st->mode != a.need_mode) return;   // uniform over the grid
   const Geom g = a.g;
@@ -694,18 +713,20 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
   const bool inside = x < nx && y < ny;
   MapRing mu;
   mu.s = su;
+  mu.init(g, n, tt.x0, tt.y0);
   HaloRing<NC> rj;
   rj.s = sj;
+  rj.init(g, tt.x0, tt.y0);
   for (int p = tt.zbeg - kBH; p < tt.zbeg + kBH; ++p) {
-    mu.fetch(UN, n, g, tt.x0, tt.y0, p);
+    mu.fetch(UN, g, p);
     mu.put(p);
   }
-  rj.fetch(JJ, n, g, tt.x0, tt.y0, tt.zbeg - 1);
+  rj.fetch(JJ, g, tt.zbeg - 1);
   rj.put(tt.zbeg - 1);
-  rj.fetch(JJ, n, g, tt.x0, tt.y0, tt.zbeg);
+  rj.fetch(JJ, g, tt.zbeg);
   rj.put(tt.zbeg);
-  mu.fetch(UN, n, g, tt.x0, tt.y0, tt.zbeg + kBH);
-  rj.fetch(JJ, n, g, tt.x0, tt.y0, tt.zbeg + 1);
+  mu.fetch(UN, g, tt.zbeg + kBH);
+  rj.fetch(JJ, g, tt.zbeg + 1);
 
   const int lx = tx + kBH, ly = ty + kBH;                    // own position in the map window
   const int jx = tx + 1, jy = ty + 1;
@@ -714,8 +735,8 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
     mu.put(z + kBH);
     rj.put(z + 1);
     __syncthreads();
-    mu.fetch(UN, n, g, tt.x0, tt.y0, z + kBH + 1);           // in flight during the step
-    rj.fetch(JJ, n, g, tt.x0, tt.y0, z + 2);
+    mu.fetch(UN, g, z + kBH + 1);                            // in flight during the step
+    rj.fetch(JJ, g, z + 2);
     if (inside) {
       const uint32_t i = (uint32_t)((z * ny + y) * nx + x);
       const int s0 = z % kBRing;
@@ -747,11 +768,11 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
       float J[3][3], ucen[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float ce = su[c][s0][ly][lx];
+        const float ce = su[s0][c][ly][lx];
         ucen[c] = ce;
-        J[c][0] = dstencil_v(su[c][s0][ly][lx + 1], su[c][s0][ly][lx - 1], ce, x, nx, ih);
-        J[c][1] = dstencil_v(su[c][s0][ly + 1][lx], su[c][s0][ly - 1][lx], ce, y, ny, ih);
-        J[c][2] = dstencil_v(su[c][sp1][ly][lx], su[c][sm1][ly][lx], ce, z, nz, ih);
+        J[c][0] = dstencil_v(su[s0][c][ly][lx + 1], su[s0][c][ly][lx - 1], ce, x, nx, ih);
+        J[c][1] = dstencil_v(su[s0][c][ly + 1][lx], su[s0][c][ly - 1][lx], ce, y, ny, ih);
+        J[c][2] = dstencil_v(su[sp1][c][ly][lx], su[sm1][c][ly][lx], ce, z, nz, ih);
       }
       J[0][0] += 1.f;
       J[1][1] += 1.f;
@@ -766,10 +787,10 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const float rw = a.w[c] * sample(RR[c], czc);
-        const float ce = sj[c][j0][jy][jx];
-        bx += rw * dstencil_v(sj[c][j0][jy][jx + 1], sj[c][j0][jy][jx - 1], ce, x, nx, ih);
-        by += rw * dstencil_v(sj[c][j0][jy + 1][jx], sj[c][j0][jy - 1][jx], ce, y, ny, ih);
-        bz += rw * dstencil_v(sj[c][jp][jy][jx], sj[c][jm][jy][jx], ce, z, nz, ih);
+        const float ce = sj[j0][c][jy][jx];
+        bx += rw * dstencil_v(sj[j0][c][jy][jx + 1], sj[j0][c][jy][jx - 1], ce, x, nx, ih);
+        by += rw * dstencil_v(sj[j0][c][jy + 1][jx], sj[j0][c][jy - 1][jx], ce, y, ny, ih);
+        bz += rw * dstencil_v(sj[jp][c][jy][jx], sj[jm][c][jy][jx], ce, z, nz, ih);
       }
       const float sc = a.coef * det;
       bst(B0, i, sc * bx);
