@@ -725,11 +725,33 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
   rj.put(tt.zbeg - 1);
   rj.fetch(JJ, g, tt.zbeg);
   rj.put(tt.zbeg);
-  mu.fetch(UN, g, tt.zbeg + kBH);
-  rj.fetch(JJ, g, tt.zbeg + 1);
 
   const int lx = tx + kBH, ly = ty + kBH;                    // own position in the map window
   const int jx = tx + 1, jy = ty + 1;
+  const uint32_t nxy = (uint32_t)(nx * ny);
+  // Residuals sampled at x + u1(x)/h on plane zz, from the staged map (plane zz in the ring).
+  auto residuals = [&](int zz, float out[NC]) {
+    const int sz = zz % kBRing;
+    const Cell czc = make_cell_zero(g, x, y, zz, su[sz][0][ly][lx] * ih, su[sz][1][ly][lx] * ih,
+                                    su[sz][2][ly][lx] * ih);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = sample(RR[c], czc);
+  };
+  // The residual samples and v of a plane are loaded one step ahead, so their
+  // latency overlaps the step before; the first plane's come before the march.
+  float rs[NC], vc[3] = {0.f, 0.f, 0.f};
+  __syncthreads();
+  if (inside) {
+    residuals(tt.zbeg, rs);
+    if (HAS_U) {
+      const uint32_t i0 = (uint32_t)tt.zbeg * nxy + (uint32_t)(y * nx + x);
+      vc[0] = bld(V0, i0);
+      vc[1] = bld(V1, i0);
+      vc[2] = bld(V2, i0);
+    }
+  }
+  mu.fetch(UN, g, tt.zbeg + kBH);
+  rj.fetch(JJ, g, tt.zbeg + 1);
   double mind = 1e300;
   for (int z = tt.zbeg; z < tt.zend; ++z) {
     mu.put(z + kBH);
@@ -740,8 +762,17 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
     if (inside) {
       const uint32_t i = (uint32_t)((z * ny + y) * nx + x);
       const int s0 = z % kBRing;
+      const int zn = z + 1 < tt.zend ? z + 1 : z;            // the next plane (the last: again)
+      float vn[3] = {0.f, 0.f, 0.f}, rn[NC];
       if (HAS_U) {
-        float vx = bld(V0, i), vy = bld(V1, i), vz = bld(V2, i);
+        const uint32_t inext = i + (zn > z ? nxy : 0u);
+        vn[0] = bld(V0, inext);
+        vn[1] = bld(V1, inext);
+        vn[2] = bld(V2, inext);
+      }
+      residuals(zn, rn);
+      if (HAS_U) {
+        float vx = vc[0], vy = vc[1], vz = vc[2];
         if (RK4) rk4_mean(V0, V1, V2, g, x, y, z, dt * ih, vx, vy, vz);
         float ux = dt * vx, uy = dt * vy, uz = dt * vz;
         int cx, cy, cz;
@@ -765,11 +796,10 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
       }
       // Jacobian matrix I + D u of u1 at time jb (rows: component, columns: direction)
       const int sm1 = (z + kBRing - 1) % kBRing, sp1 = (z + 1) % kBRing;
-      float J[3][3], ucen[3];
+      float J[3][3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float ce = su[s0][c][ly][lx];
-        ucen[c] = ce;
         J[c][0] = dstencil_v(su[s0][c][ly][lx + 1], su[s0][c][ly][lx - 1], ce, x, nx, ih);
         J[c][1] = dstencil_v(su[s0][c][ly + 1][lx], su[s0][c][ly - 1][lx], ce, y, ny, ih);
         J[c][2] = dstencil_v(su[sp1][c][ly][lx], su[sm1][c][ly][lx], ce, z, nz, ih);
@@ -781,12 +811,11 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
       mind = fmin(mind, (double)det);
-      const Cell czc = make_cell_zero(g, x, y, z, ucen[0] * ih, ucen[1] * ih, ucen[2] * ih);
       const int j0 = z % 3, jm = (z + 2) % 3, jp = (z + 1) % 3;
       float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const float rw = a.w[c] * sample(RR[c], czc);
+        const float rw = a.w[c] * rs[c];
         const float ce = sj[j0][c][jy][jx];
         bx += rw * dstencil_v(sj[j0][c][jy][jx + 1], sj[j0][c][jy][jx - 1], ce, x, nx, ih);
         by += rw * dstencil_v(sj[j0][c][jy + 1][jx], sj[j0][c][jy - 1][jx], ce, y, ny, ih);
@@ -796,6 +825,10 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
       bst(B0, i, sc * bx);
       bst(B1, i, sc * by);
       bst(B2, i, sc * bz);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vc[c] = vn[c];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) rs[c] = rn[c];
     }
     __syncthreads();
   }
