@@ -260,22 +260,24 @@ __device__ __forceinline__ void fft_stage(float2* sm, int N, int ls, int nl, int
   const int total = nl * nb;
   const int step = N / (Ns * R);
   float2 val[NB][R];
-  int line[NB], jj[NB];
+  int line[NB], jq[NB], kk[NB];     // butterfly j = jq Ns + k of line l, kept across the barrier
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     const int bi = threadIdx.x + t * kBlock;
     line[t] = -1;
-    jj[t] = 0;
+    jq[t] = 0;
+    kk[t] = 0;
     if (bi < total) {
       const int l = (int)fdiv((uint32_t)bi, fnb);
       const int j = bi - l * nb;
       line[t] = l;
-      jj[t] = j;
+      jq[t] = (int)fdiv((uint32_t)j, fns);
+      kk[t] = j - jq[t] * Ns;
       const float2* src = sm + l * ls + j;
 #pragma unroll
       for (int q = 0; q < R; ++q) val[t][q] = src[q * nb];
       if (Ns > 1) {
-        const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
+        const int k = kk[t];
 #pragma unroll
         for (int q = 1; q < R; ++q) val[t][q] = cmul(val[t][q], tw[q * k * step]);
       }
@@ -285,11 +287,8 @@ __device__ __forceinline__ void fft_stage(float2* sm, int N, int ls, int nl, int
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     if (line[t] >= 0) {
-      const int j = jj[t];
-      const int jq = (int)fdiv((uint32_t)j, fns);
-      const int k = j - jq * Ns;
       radix_dft<R>(val[t]);
-      float2* dst = sm + line[t] * ls + jq * Ns * R + k;
+      float2* dst = sm + line[t] * ls + jq[t] * Ns * R + kk[t];
 #pragma unroll
       for (int q = 0; q < R; ++q) dst[q * Ns] = val[t][q];
     }
