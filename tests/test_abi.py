@@ -107,6 +107,28 @@ def test_profile_classes_match_header():
         assert int(re.search(rf"#define LDDMM_PROF_{name}\s+(\d+)", src).group(1)) == k
 
 
+def test_tunable_ids_match_header_and_values_are_checked():
+    # process-wide launch shapes; setting them touches no GPU
+    from paper_1605_02060_amd import tune
+    src = open(os.path.join(ROOT, "include", "lddmm.h")).read()
+    for name in ("SWEEP_BLOCKS", "FFT_X_ELEMS", "FFT_COLS", "FFT_ZCOLS", "STAGED_MIN_BLOCKS",
+                 "FWD_TILES"):
+        val = int(re.search(rf"#define LDDMM_TUNE_{name}\s+(\d+)", src).group(1))
+        assert getattr(L, f"TUNE_{name}") == val
+    assert set(tune.DEFAULTS) == set(tune.CANDIDATES) == set(tune.NAMES)
+    try:
+        with pytest.raises(RuntimeError):
+            L.lddmm_set_tunable(L.TUNE_FWD_TILES, -1)
+        with pytest.raises(RuntimeError):
+            L.lddmm_set_tunable(L.TUNE_SWEEP_BLOCKS, 0)
+        with pytest.raises(RuntimeError):
+            L.lddmm_set_tunable(99, 1)
+        L.lddmm_set_tunable(L.TUNE_FWD_TILES, 0)          # 0: the grid-stride forward sweep
+        L.lddmm_set_tunable(L.TUNE_FWD_TILES, 1 << 20)    # clamped to the partial buffers
+    finally:
+        tune.set_all(tune.DEFAULTS)
+
+
 def test_energy_and_gradient_take_v_on_the_single_level_grid():
     # the library evaluates energy and gradient on one level whatever n_levels
     # says, so the binding checks v against the single-level grid
