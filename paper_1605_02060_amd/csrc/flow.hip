@@ -737,13 +737,14 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
 #pragma unroll
     for (int c = 0; c < NC; ++c) out[c] = sample(RR[c], czc);
   };
-  // The residual samples and v of a plane are loaded one step ahead, so their
-  // latency overlaps the step before; the first plane's come before the march.
+  // With a map to compute, the residual samples and v of a plane are loaded one
+  // step ahead, so their latency overlaps the step before; the first plane's
+  // come before the march.  The last step (no map) samples in its own step.
   float rs[NC], vc[3] = {0.f, 0.f, 0.f};
-  __syncthreads();
-  if (inside) {
-    residuals(tt.zbeg, rs);
-    if (HAS_U) {
+  if (HAS_U) {
+    __syncthreads();
+    if (inside) {
+      residuals(tt.zbeg, rs);
       const uint32_t i0 = (uint32_t)tt.zbeg * nxy + (uint32_t)(y * nx + x);
       vc[0] = bld(V0, i0);
       vc[1] = bld(V1, i0);
@@ -769,8 +770,10 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
         vn[0] = bld(V0, inext);
         vn[1] = bld(V1, inext);
         vn[2] = bld(V2, inext);
+        residuals(zn, rn);
+      } else {
+        residuals(z, rs);
       }
-      residuals(zn, rn);
       if (HAS_U) {
         float vx = vc[0], vy = vc[1], vz = vc[2];
         if (RK4) rk4_mean(V0, V1, V2, g, x, y, z, dt * ih, vx, vy, vz);
@@ -825,10 +828,12 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
       bst(B0, i, sc * bx);
       bst(B1, i, sc * by);
       bst(B2, i, sc * bz);
+      if (HAS_U) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) vc[c] = vn[c];
+        for (int c = 0; c < 3; ++c) vc[c] = vn[c];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) rs[c] = rn[c];
+        for (int c = 0; c < NC; ++c) rs[c] = rn[c];
+      }
     }
     __syncthreads();
   }
