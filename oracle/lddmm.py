@@ -493,6 +493,8 @@ def gradient_V(v, st, prm: Params, h):
     b_j = (2/sigma^2) det(D phi_{j,1}) sum_c w_c (r_c o phi_{j,1}) grad(J0c o phi_{j,0}),
     with r_c = J0c o phi_10 - J1c back-transported by the backward map u1[j].
     Returns (g [T,3,...], min over j, x of det).
+    Pinned by closed forms of b_j: a whole-voxel translation, an affine
+    velocity with linear images, and v = 0 (tests/test_oracle_gradient_pins.py).
     """
     T = v.shape[0]
     X = index_positions(v.shape[2:])

@@ -195,11 +195,12 @@ def test_exact_gradient_matches_bruteforce_fd_on_non_cubic_grid():
     assert np.abs(g - fd).max() < 2e-6 * np.abs(g).max()
 
 
-def test_exact_gradient_directional_fd_physical_spacing():
+@pytest.mark.parametrize("sigma", [1.0, 0.5])
+def test_exact_gradient_directional_fd_physical_spacing(sigma):
     prob = _tiny_problem(11, 10)
     T = 3
     h = 0.05
-    prm = O.Params(T=T, spacing=h)
+    prm = O.Params(T=T, spacing=h, sigma=sigma, weight=(1.0, 0.5))
     J0, J1, P = O._single_level(prob)
     v = h * _smooth_v(T, P, 12, 1.0)
     d = h * _smooth_v(T, P, 13, 1.0)
@@ -211,13 +212,14 @@ def test_exact_gradient_directional_fd_physical_spacing():
     assert abs(fd - (g * d).sum()) < 1e-5 * abs(fd)
 
 
-def test_plain_gradient_is_K_of_exact_gradient_to_discretisation_error():
+@pytest.mark.parametrize("sigma", [1.0, 0.5])
+def test_plain_gradient_is_K_of_exact_gradient_to_discretisation_error(sigma):
     # Beg's V-gradient g satisfies K^-1 g ~ dE/dv / (dt h^3) up to O(dt, h) terms:
     # compare the two as directional derivatives along smooth directions.
     p = synth.blob_pair((16, 16, 16), 14, max_disp=1.5, sigma=(2.5, 4.0), center_frac=(0.3, 0.7))
     prob = O.Problem(p.I0, p.I1)
     T = 8
-    prm = O.Params(T=T, alpha=0.5, weight=(1.0, 0.0))
+    prm = O.Params(T=T, alpha=0.5, sigma=sigma, weight=(1.0, 0.0))
     J0, J1, P = O._single_level(prob)
     v = _smooth_v(T, P, 15, 0.6) * 3.0
     gV, _, _ = O.gradient(prob, prm, v, kind="V")
