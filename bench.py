@@ -30,7 +30,13 @@ HBM_PEAK_GBS = 8000.0
 #  forward step : read v 12, read u0 12, gather J0 4, write u0 12, write J0_t 4
 #  backward step: read v 12, read u1 12, write u1 12, gather r 4, read J0_t 4, write b 12
 #  K (all five passes together): read b 12, write K b 12; update: read v 12, K b 12, write v 12
-ALG_BYTES = {"forward": 44.0, "backward": 56.0}
+#  each FFT pass on its own: read and write its operand once (x inverse: + v read and write)
+ALG_BYTES = {"forward": 44.0, "backward": 56.0, "fft_x": 24.0, "fft_y": 24.0, "fft_zK": 24.0,
+             "fft_yinv": 24.0, "fft_xinv_update": 36.0}
+K_CHAIN = ("fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update")
+K_CHAIN_ALG_BYTES = 60.0    # K as one round trip (24) + the update (36), per voxel-timestep
+SWEEP_CLASSES = ("forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv",
+                 "fft_xinv_update", "forward_edge", "backward_edge")
 B_ALG_PATH = 162.0          # per voxel-timestep per iteration, whole path
 
 LEVELS = 3
@@ -80,6 +86,28 @@ def attainable_bandwidth(torch, L, nbytes=None, reps=10):
     gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
     return gbs
+
+
+def kernel_name(cls, tunables, rk4, nch=1):
+    """The kernel a profile class launches at the finest atlas level (as the rocprofv3
+    summaries name it), given the launch-shape choice."""
+    b = lambda x: "true" if x else "false"
+    if cls == "forward":
+        zm = tunables.get("fwd_tiles", 3584) > 0
+        return f"k_forward<{nch}, false, false, {b(rk4)}, {b(zm)}>"
+    if cls == "backward":
+        if tunables.get("staged_min_blocks", 2048) <= 3200:   # 3200 staged blocks at 280x160x240
+            return f"k_backward_staged<{nch}, true, {b(rk4)}>"
+        return f"k_backward<{nch}, true, false, true, {b(rk4)}>"
+    return {"fft_x": "k_fft_x_fwd", "fft_y": "k_fft_y<*, false>", "fft_zK": "k_fft_z_K",
+            "fft_yinv": "k_fft_y<*, true>", "fft_xinv_update": "k_fft_x_inv"}.get(cls, cls)
+
+
+def last_accepted_D(tr):
+    """Masked SSD term D of the current iterate at the end: the D of the last
+    accepted trial (a rejected or stopped slot's D is not the iterate's)."""
+    ok = np.where((tr[:, 6] == 1) & np.isfinite(tr[:, 2]))[0]
+    return float(tr[ok[-1], 2]) if len(ok) else float("nan")
 
 
 def work_units(shape):
@@ -208,18 +236,20 @@ def summarize_profile(db, out_path, command):
 
 
 def library_sources_sha():
-    """SHA-256 of what builds the measured sweep kernels (the forward and backward
-    sweeps): their sources and the compiler flags of flow.hip (paths left out), to
-    tell whether stored counters describe them."""
+    """SHA-256 of what builds the measured kernels (the sweeps and the FFT passes):
+    their sources and compiler flags (paths left out), to tell whether stored
+    counters describe them."""
     import hashlib
     from paper_1605_02060_amd import build as B
     hsh = hashlib.sha256()
-    for rel in ("paper_1605_02060_amd/csrc/flow.hip", "paper_1605_02060_amd/csrc/internal.h",
+    for rel in ("paper_1605_02060_amd/csrc/flow.hip", "paper_1605_02060_amd/csrc/fft.hip",
+                "paper_1605_02060_amd/csrc/device.h", "paper_1605_02060_amd/csrc/internal.h",
                 "include/lddmm.h"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             hsh.update(rel.encode())
             hsh.update(f.read())
-    hsh.update(" ".join(f for f in B.flags_for("flow.hip") if not os.path.isabs(f)).encode())
+    for src in ("flow.hip", "fft.hip"):
+        hsh.update(" ".join(f for f in B.flags_for(src) if not os.path.isabs(f)).encode())
     return hsh.hexdigest()
 
 
@@ -289,7 +319,12 @@ def compute_traffic(fetch_db, write_db, out_path):
     # autotuner's trials of other shapes).  Grids alone do not tell the levels
     # apart: plane-marching launches size their grid by planes and runs, so a
     # coarser level can launch more blocks.
-    classes = {"forward": r"^void k_forward<", "backward": r"^void k_backward(_staged)?<"}
+    # one kernel per class, as the profile classes of the bench line count them
+    classes = {"forward": r"^void k_forward<\d+, false, false,",
+               "backward": r"^void k_backward(_staged<\d+, true,|<\d+, true, false, true,)",
+               "fft_x": r"^void k_fft_x_fwd<", "fft_y": r"^void k_fft_y<\d+, false>",
+               "fft_zK": r"^void k_fft_z_K<", "fft_yinv": r"^void k_fft_y<\d+, true>",
+               "fft_xinv_update": r"^void k_fft_x_inv<"}
     for cls, pat in classes.items():
         tot = {"fetch": [], "write": []}
         durs = []
@@ -861,20 +896,24 @@ def main():
         v.zero_()
         return L.lddmm_register(M0, M1, MI0, MI1, params=prm, spacing=SPACING, v=v, ws=ws)
 
-    # warmup; the first warmup step times every kernel class to find the dominant one
+    # warmup; the first warmup step times every kernel class of the finest level, to
+    # find the kernel with the largest total time and the K chain's time per step
     prof = None
+    sweep_mask = sum(1 << L.PROF_CLASSES.index(c) for c in SWEEP_CLASSES)
     for w in range(max(args.warmup, 1)):
         if w == 0:
-            L.lddmm_profile_begin(0xFF, n_fine)
+            L.lddmm_profile_begin(sweep_mask, n_fine)
         res = step()
         torch.cuda.synchronize()
         if w == 0:
             prof = L.lddmm_profile_end()
         log(f"warmup {w} done, status {res['status']}")
-    dominant = max(("forward", "backward"), key=lambda k: prof[k]["ms"])
+    # each class below is one kernel at the finest level (the edge classes hold the
+    # first and last steps of a sweep, two kernels each, and are not candidates)
+    dominant = max(ALG_BYTES, key=lambda k: prof[k]["ms"])
     cls_bit = 1 << L.PROF_CLASSES.index(dominant)
 
-    # timed region: exactly K steps, HIP events around the dominant kernel class
+    # timed region: exactly K steps, HIP events around the dominant kernel
     L.lddmm_profile_begin(cls_bit, n_fine)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -889,14 +928,18 @@ def main():
 
     tr = res["trace"].cpu().numpy()
     rej = int((tr[:, 6] == 0).sum())
-    final_D = float(tr[-1, 2]) if np.isfinite(tr[-1, 2]) else float(tr[-1, 7])
+    user_fine = int(np.prod(pair.shape))             # user voxels of the finest level
     avg_ms = live["ms"] / max(live["launches"], 1)
     vox_per_launch = live["voxels"] / max(live["launches"], 1)
-    achieved = ALG_BYTES[dominant] * vox_per_launch / (avg_ms * 1e-3) / 1e9
+    achieved = ALG_BYTES[dominant] * user_fine / (avg_ms * 1e-3) / 1e9
+    achieved_padded = ALG_BYTES[dominant] * vox_per_launch / (avg_ms * 1e-3) / 1e9
     total_ms = sum(x["ms"] for x in prof.values())
-    shares = {k: round(x["ms"] / total_ms, 4) for k, x in prof.items()}
+    shares = {k: round(x["ms"] / total_ms, 4) for k, x in prof.items() if x["launches"]}
     per_launch_us = {k: round(1000.0 * x["ms"] / x["launches"], 2)
                      for k, x in prof.items() if x["launches"]}
+    chain_ms = sum(prof[k]["ms"] / prof[k]["launches"] for k in K_CHAIN)
+    chain_gbs = K_CHAIN_ALG_BYTES * user_fine / (chain_ms * 1e-3) / 1e9
+    rk4 = FLAGS != 0
 
     out = {
         "metric": "voxel-timestep updates/s (flow+adjoint+K); time to target masked SSD",
@@ -914,12 +957,24 @@ def main():
         "config": dict(workload_config(), tunables=tunables),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(dominant) if FLAGS == 0 else None,
+                     "traffic": stored_traffic(dominant) if not rk4 else None,
                      "attainable": attainable, "frac_of_attainable": achieved / attainable,
-                     "kernel": f"k_{dominant}", "alg_bytes_per_voxel": ALG_BYTES[dominant],
-                     "measured_on": "finest-level launches (280x160x240 grid) of the timed steps",
-                     "avg_launch_ms": avg_ms, "launches": live["launches"],
-                     "voxels_per_launch": vox_per_launch},
+                     "kernel": kernel_name(dominant, tunables, rk4),
+                     "profile_class": dominant,
+                     "alg_bytes_per_voxel": ALG_BYTES[dominant],
+                     "voxels": "user voxels of the finest level (264x160x228); the kernel "
+                               "runs on the padded 280x160x240 grid",
+                     "user_voxels_per_launch": user_fine,
+                     "padded_voxels_per_launch": vox_per_launch,
+                     "achieved_on_padded_voxels": achieved_padded,
+                     "frac_on_padded_voxels": achieved_padded / HBM_PEAK_GBS,
+                     "measured_on": "finest-level launches of the timed steps (HIP events on the "
+                                    "launch stream)",
+                     "avg_launch_ms": avg_ms, "launches": live["launches"]},
+        "k_chain": {"passes": list(K_CHAIN), "alg_bytes_per_voxel": K_CHAIN_ALG_BYTES,
+                    "us_per_time_step": 1000.0 * chain_ms, "achieved_GBs": chain_gbs,
+                    "frac": chain_gbs / HBM_PEAK_GBS,
+                    "measured_on": "finest-level launches of the first warmup step"},
         "path_roofline": {"alg_bytes_per_voxel_timestep": B_ALG_PATH,
                           "achieved_GBs": value * B_ALG_PATH / 1e9,
                           "frac": value * B_ALG_PATH / 1e9 / HBM_PEAK_GBS},
@@ -927,7 +982,7 @@ def main():
         "finest_level_us_per_launch": per_launch_us,
         "level_final_E": [float(tr[i, 7]) for i in np.cumsum([it + 1 for it in ITERS]) - 1],
         "time_to_target_s": ms_per_step / 1000.0,
-        "target_masked_ssd": final_D,
+        "target_masked_ssd": last_accepted_D(tr),
         "rejected_slots": rej,
         "status": res["status"],
     }

@@ -48,7 +48,9 @@ extern "C" {
                                  alpha/gamma/sigma/spacing <= 0, workspace too small */
 #define LDDMM_EHIP       -2   /* HIP runtime or launch error */
 #define LDDMM_ENONFINITE -3   /* energy not finite (NaN/Inf velocity or inputs) */
-#define LDDMM_WFOLD       1   /* warning: min det D(phi_{t,1}) <= 0 seen; result written */
+#define LDDMM_WFOLD       1   /* warning: the returned v folds: min over j < T and the
+                                 finest computational grid of det D(phi_{t_j,1}) <= 0
+                                 (np.gradient stencil); result written */
 #define LDDMM_WGUARD      2   /* warning: a level stopped after LDDMM_MAX_HALVINGS step halvings */
 
 #define LDDMM_GRAD_V      0   /* Beg's gradient in V: g_j = 2 v_j - K b_j */
@@ -129,7 +131,11 @@ int32_t lddmm_trace_rows(const lddmm_params *params);
  * with guard=1 a trial is accepted iff its energy does not exceed the current
  * one.  v is upsampled (cell-centred trilinear) between levels.  The guard is
  * decided on the device; the call synchronises `stream` once at exit and
- * returns LDDMM_OK, a warning (LDDMM_WFOLD / LDDMM_WGUARD) or an error.
+ * returns LDDMM_OK, a warning or an error, in this order of precedence:
+ * LDDMM_ENONFINITE (non-finite energy), LDDMM_WGUARD (a level stopped on the
+ * guard), LDDMM_WFOLD (the returned v's maps phi_{t_j,1} fold; after the
+ * descent, one forward and one backward sweep of the returned v at the finest
+ * level take the minimum of det(I + D u1_j) over j < T and the grid).
  * With n_problems > 1 the call is lddmm_register_batched(p, n, params, NULL, stream)
  * and returns the most severe status of the batch.
  */
@@ -316,8 +322,10 @@ int lddmm_histogram_match(const lddmm_grid *src_grid, const float *src, const fl
  * number of grid voxels those launches covered (arrays of LDDMM_PROF_CLASSES,
  * host memory, may be NULL) and stops recording.  Not thread-safe.
  */
-#define LDDMM_PROF_FORWARD   0   /* forward map step + template warp + energy partials */
-#define LDDMM_PROF_BACKWARD  1   /* backward map step + Jacobian + body force */
+#define LDDMM_PROF_FORWARD   0   /* forward map step + template warp + energy partials,
+                                    interior steps 0 < j < T-1 */
+#define LDDMM_PROF_BACKWARD  1   /* backward map step + Jacobian + body force, the steps
+                                    that compute both a map and a body force */
 #define LDDMM_PROF_FFT_X     2   /* x forward pass of K (real -> half spectrum) */
 #define LDDMM_PROF_FFT_Y     3   /* y forward pass */
 #define LDDMM_PROF_FFT_ZK    4   /* z pass: forward, K_hat, inverse */
@@ -328,7 +336,11 @@ int lddmm_histogram_match(const lddmm_grid *src_grid, const float *src, const fl
 #define LDDMM_PROF_HIST_COUNT  9 /* histogram matching: bin counts, totals, point table (three launches) */
 #define LDDMM_PROF_HIST_APPLY 10 /* histogram matching: intensity map */
 #define LDDMM_PROF_ALIGN     11  /* pre-alignment: MSE and gradient pass */
-#define LDDMM_PROF_CLASSES   12
+#define LDDMM_PROF_FORWARD_EDGE  12  /* forward steps j = 0 and j = T-1 (the last also
+                                        forms the residual and the data terms) */
+#define LDDMM_PROF_BACKWARD_EDGE 13  /* backward steps with a map but no body force
+                                        (the first) or a body force but no map (the last) */
+#define LDDMM_PROF_CLASSES   14
 int lddmm_profile_begin(uint32_t class_mask, int64_t min_voxels);
 int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 

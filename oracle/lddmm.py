@@ -639,6 +639,9 @@ def register(problem: Problem, prm: Params, v_init=None):
     """Masked LDDMM registration (Methods, Registration), coarse-to-fine.
 
     Inputs are pre-aligned template/target channels on the user grid N.
+    Status: ENONFINITE, else WGUARD if a level stopped on the guard, else WFOLD
+    if the returned v folds (min over j < T and the finest computational grid
+    of det(I + D u1_j) <= 0), else OK.
     v_init (optional) is [T, 3, *P_finest]; for several levels it is block-
     averaged down to the coarsest level.  Returns v on the finest computational
     grid, phi10 - id = u0_T and phi01 - id = u1_0 cropped to N, the per-slot
@@ -667,15 +670,13 @@ def register(problem: Problem, prm: Params, v_init=None):
             v = np.stack([np.stack([downsample2(v[j, c]) for c in range(3)]) for j in range(T)])
     trace = []
     status = STATUS_OK
-    worst_det = math.inf
     for li, g in enumerate(grids):
         if li > 0:
             v = np.stack([np.stack([upsample2_clamp(v[j, c], g["P"]) for c in range(3)])
                           for j in range(T)])
         iters = prm.iters[li] if li < len(prm.iters) else prm.iters[-1]
-        v, st, s, md = _level_loop(v, pyr0[li], pyr1[li], prm, prm.spacing * g["h"], iters,
-                                   trace)
-        worst_det = min(worst_det, md)
+        v, st, s, _ = _level_loop(v, pyr0[li], pyr1[li], prm, prm.spacing * g["h"], iters,
+                                  trace)
         if s == STATUS_ENONFINITE:
             status = s
             break
@@ -691,7 +692,10 @@ def register(problem: Problem, prm: Params, v_init=None):
     u1 = backward_maps(v, h, prm.integrator)
     phi10 = st["u0"][T][:, :nz, :ny, :nx]
     phi01 = u1[0][:, :nz, :ny, :nx]
-    if status == STATUS_OK and worst_det <= 0.0:
+    # a fold of the returned result: det D phi_{t_j,1} <= 0 for some j < T, anywhere
+    # on the finest computational grid, for the final v
+    final_det = min(float(jacobian_det(u1[j], h).min()) for j in range(T))
+    if status == STATUS_OK and final_det <= 0.0:
         status = STATUS_WFOLD
     return Result(v=v, phi10=phi10, phi01=phi01, trace=trace, status=status, levels=grids)
 

@@ -15,7 +15,7 @@ __global__ void k_level_begin(State* st, double step, int keep_flags) {
     st->row = 0;
     st->stopped_any = 0;
     st->nonfinite = 0;
-    st->min_det_all = 1e300;
+    st->min_det_final = 1e300;
   }
   st->eps = step;
   st->step0 = step;
@@ -121,10 +121,7 @@ __device__ __forceinline__ void decide_body(State* st, const double* partR, int 
     }
     return;
   }
-  if (mode == MODE_GRAD) {
-    st->min_det = md;
-    st->min_det_all = fmin(st->min_det_all, md);
-  }
+  if (mode == MODE_GRAD) st->min_det = md;
   const double used = st->eps;
   const bool ok = !guard || (Et <= st->E);
   if (ok) {
@@ -218,6 +215,20 @@ void launch_retry(float* vA, float* vB, long long count, const State* st, hipStr
   long long b = (count + kBlock - 1) / kBlock;
   if (b > 65536) b = 65536;
   hipLaunchKernelGGL(k_retry, dim3((unsigned)b), dim3(kBlock), 0, s, vA, vB, count, st);
+}
+
+// Min det D phi_{t_j,1} over j < T and the grid, from the body-force steps of a
+// backward sweep of the returned velocity (partials of jb = 0 .. T-1).
+__global__ __launch_bounds__(1024) void k_final_det(State* st, const double* partDet, int T,
+                                                    int nbw) {
+  __shared__ double red[1024];
+  double md = 1e300;
+  for (int j = 0; j < T; ++j) md = fmin(md, block1024_min(partDet + (long long)j * kPartMax, nbw, red));
+  if (threadIdx.x == 0) st->min_det_final = md;
+}
+
+void launch_final_det(State* st, const double* partDet, int T, int nbw, hipStream_t s) {
+  hipLaunchKernelGGL(k_final_det, dim3(1), dim3(1024), 0, s, st, partDet, T, nbw);
 }
 
 __global__ void k_energy_out(const State* st, double* out4) {

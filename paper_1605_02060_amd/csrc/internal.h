@@ -82,7 +82,8 @@ struct State {
   int pad0;
   double eps, step0;
   double E, R, D, img;       // energy terms of the current iterate
-  double min_det, min_det_all;
+  double min_det;            // min det of the last gradient evaluation (trace column)
+  double min_det_final;      // min det of the returned v's maps (LDDMM_WFOLD)
 };
 
 // --------------------------------------------------------------- sweeps ----
@@ -294,5 +295,6 @@ void launch_retry(float* vA, float* vB, long long count, const State* st, hipStr
 void launch_decide_batched(const BatchRef& br, int init, hipStream_t s);
 void launch_retry_batched(const BatchRef& br, hipStream_t s);
 void launch_energy_out(const State* st, double* out4, hipStream_t s);
+void launch_final_det(State* st, const double* partDet, int T, int nbw, hipStream_t s);
 
 }  // namespace lddmm

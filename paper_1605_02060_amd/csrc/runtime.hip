@@ -352,7 +352,7 @@ static void forward_steps(Ctx& c, int li, const float* vA, const float* vB, cons
     a.st = c.st;
     a.rk4 = k.rk4;
     a.zmarch = forward_zmarch(L.g);
-    ProfScope ps(LDDMM_PROF_FORWARD, n, s);
+    ProfScope ps((j == 0 || j == k.T - 1) ? LDDMM_PROF_FORWARD_EDGE : LDDMM_PROF_FORWARD, n, s);
     launch_forward(a, s);
   }
 }
@@ -422,7 +422,8 @@ static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, h
 // Backward sweep: maps u1_j, body forces b_j, K b_j and the epilogue per j.
 // With with_grad = false only the maps are computed (u1_0 ends in slot 0).
 static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vfix, bool with_grad,
-                           int upd_kind, float* gout, int need_mode, hipStream_t s) {
+                           int upd_kind, float* gout, int need_mode, hipStream_t s,
+                           bool smooth = true) {
   const Config& k = c.cfg;
   const Level& L = k.lv[li];
   const long long n = L.g.n;
@@ -460,10 +461,11 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
     a.staged = backward_staged(L.g);
     if (a.j < 0 && a.jb < 0) continue;
     {
-      ProfScope ps(LDDMM_PROF_BACKWARD, n, s);
+      const bool both = a.j >= 0 && a.u_next != nullptr && a.jb >= 0;
+      ProfScope ps(both ? LDDMM_PROF_BACKWARD : LDDMM_PROF_BACKWARD_EDGE, n, s);
       launch_backward(a, s);
     }
-    if (a.jb >= 0) {
+    if (a.jb >= 0 && smooth) {
       UpdArgs u{};
       u.kind = upd_kind;
       u.j = a.jb;
@@ -479,6 +481,22 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
 }
 
 static void decide(Ctx& c, int li, int init, double* trace, hipStream_t s);
+
+// Outputs of the final iterate (buffer 0) at the finest level: phi_10 (if asked),
+// phi_01 (if asked) and the min det of its maps phi_{t_j,1}, which decides
+// LDDMM_WFOLD.  The forward sweep gives the deformed templates and the residual
+// the body-force steps read; the body forces themselves are discarded.
+static void final_outputs(Ctx& c, float* phi10, float* phi01, hipStream_t s) {
+  const Config& k = c.cfg;
+  const int top = k.L - 1;
+  const Level& L = k.lv[top];
+  forward_sweep(c, top, c.v[0], c.v[1], false, s);
+  if (phi10)
+    launch_crop3(u0_final(c, top, false), L.g, L.N[0], L.N[1], L.N[2], phi10, s);
+  backward_sweep(c, top, c.v[0], c.v[1], c.v[0], true, UPD_STEP, nullptr, -1, s, false);
+  launch_final_det(c.st, c.partDet, k.T, backward_partials(L.g), s);
+  if (phi01) launch_crop3(c.u1, L.g, L.N[0], L.N[1], L.N[2], phi01, s);
+}
 
 // Exact gradient dE/dv (reverse mode) of the single-level energy at v.
 static void exact_gradient(Ctx& c, const float* v, float* grad, hipStream_t s) {
@@ -718,15 +736,7 @@ int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm
   canonicalize(c, 3 * nf * k.T, s);
   launch_copy(c.v[0], p->v, 3 * nf * k.T, s);
   hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, c.st, 0, (int)MODE_INIT);
-  if (p->phi10) {
-    forward_sweep(c, top, c.v[0], c.v[1], false, s);
-    launch_crop3(u0_final(c, top, false), k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1],
-                 k.lv[top].N[2], p->phi10, s);
-  }
-  if (p->phi01) {
-    backward_sweep(c, top, c.v[0], c.v[1], c.v[0], false, UPD_STEP, nullptr, -1, s);
-    launch_crop3(c.u1, k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1], k.lv[top].N[2], p->phi01, s);
-  }
+  final_outputs(c, p->phi10, p->phi01, s);
   rc = hip_status();
   if (rc) return rc;
   State hs{};
@@ -741,7 +751,7 @@ int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm
     return LDDMM_ENONFINITE;
   }
   if (hs.stopped_any) return LDDMM_WGUARD;
-  if (hs.min_det_all <= 0.0) return LDDMM_WFOLD;
+  if (hs.min_det_final <= 0.0) return LDDMM_WFOLD;
   return LDDMM_OK;
 }
 
@@ -981,16 +991,7 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
     canonicalize(c, 3 * nf * k.T, s);
     launch_copy(c.v[0], pr->v, 3 * nf * k.T, s);
     hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, c.st, 0, (int)MODE_INIT);
-    if (pr->phi10) {
-      forward_sweep(c, top, c.v[0], c.v[1], false, s);
-      launch_crop3(u0_final(c, top, false), k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1],
-                   k.lv[top].N[2], pr->phi10, s);
-    }
-    if (pr->phi01) {
-      backward_sweep(c, top, c.v[0], c.v[1], c.v[0], false, UPD_STEP, nullptr, -1, s);
-      launch_crop3(c.u1, k.lv[top].g, k.lv[top].N[0], k.lv[top].N[1], k.lv[top].N[2], pr->phi01,
-                   s);
-    }
+    final_outputs(c, pr->phi10, pr->phi01, s);
     if (pr->trace) {
       const int rows = trace_rows(prm);
       hipMemcpyAsync(pr->trace, c.trace, sizeof(double) * 8 * rows, hipMemcpyDeviceToDevice, s);
@@ -1014,7 +1015,7 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
       st = LDDMM_ENONFINITE;
     } else if (hs[p].stopped_any) {
       st = LDDMM_WGUARD;
-    } else if (hs[p].min_det_all <= 0.0) {
+    } else if (hs[p].min_det_final <= 0.0) {
       st = LDDMM_WFOLD;
     }
     if (status) status[p] = st;

@@ -157,7 +157,8 @@ TUNE_STAGED_MIN_BLOCKS = 4
 TUNE_FWD_TILES = 5
 
 PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
-                "other", "hist_range", "hist_count", "hist_apply", "align"]
+                "other", "hist_range", "hist_count", "hist_apply", "align", "forward_edge",
+                "backward_edge"]
 
 
 def strerror(code):
@@ -601,7 +602,7 @@ def lddmm_surface_distance(mask_a, mask_b, spacing=1.0, ws=None, stream=None):
     return out
 
 
-def lddmm_profile_begin(class_mask=0xFFF, min_voxels=0):
+def lddmm_profile_begin(class_mask=(1 << 14) - 1, min_voxels=0):
     """Record HIP events around every launch of the selected kernel classes
     whose grid has at least min_voxels voxels."""
     _check(load().lddmm_profile_begin(int(class_mask), int(min_voxels)), "lddmm_profile_begin")

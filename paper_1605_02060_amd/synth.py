@@ -40,6 +40,7 @@ __all__ = [
     "atlas_pair",
     "random_velocity",
     "random_direction",
+    "plane_wave_velocity",
     "batched_dims",
     "config_pair",
 ]
@@ -280,6 +281,23 @@ def random_velocity(shape, T, seed, vmax=2.0, sigma_s=8.0):
         mag = np.sqrt((v[j] ** 2).sum(axis=0)).max()
         v[j] *= vmax / mag
     return v.astype(np.float32)
+
+
+def plane_wave_velocity(grid, seed, vmax):
+    """A smooth periodic field [3, nz, ny, nx] (float64) on a computational grid:
+    per component four plane waves sin(2 pi k.x/P + p) with integer k in [1, 3]^3
+    and random phase, scaled so that max_x |v_c(x)| == vmax for each component."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64) / n for n in grid), indexing="ij",
+                          sparse=True)
+    out = np.zeros((3,) + tuple(grid), dtype=np.float64)
+    for c in range(3):
+        for _ in range(4):
+            k = rng.integers(1, 4, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            out[c] += np.sin(2 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+        out[c] *= vmax / np.abs(out[c]).max()
+    return out
 
 
 def random_direction(shape, T, seed, vmax=1.0, sigma_s=8.0):

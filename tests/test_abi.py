@@ -103,7 +103,7 @@ def test_profile_classes_match_header():
     assert len(L.PROF_CLASSES) == n
     for k, name in enumerate(("FORWARD", "BACKWARD", "FFT_X", "FFT_Y", "FFT_ZK", "FFT_YINV",
                               "FFT_XINV", "OTHER", "HIST_RANGE", "HIST_COUNT", "HIST_APPLY",
-                              "ALIGN")):
+                              "ALIGN", "FORWARD_EDGE", "BACKWARD_EDGE")):
         assert int(re.search(rf"#define LDDMM_PROF_{name}\s+(\d+)", src).group(1)) == k
 
 

@@ -45,8 +45,8 @@ def _rows(copy_kib, fwd_kib, bwd_kib):
     rows += [(zm, 450560, 22000, fwd_kib / 8)] * 6
     rows += [(zm, 897024, 185000, 1.5 * fwd_kib)] * 2
     # staged backward at the finest level only; a map-only step at the finest level
-    # (60 % of the bytes); a grid-stride body-force variant that runs only on a
-    # coarser level (left out)
+    # (60 % of the bytes, another profile class); a grid-stride body-force variant
+    # that runs only on a coarser level (left out)
     rows += [("void lddmm::k_backward_staged<1, true, false>(lddmm::BwdArgs)", 737280, 205000,
               bwd_kib)] * 4
     rows += [("void lddmm::k_backward<1, true, true, false, false>(lddmm::BwdArgs)", 262144,
@@ -75,9 +75,11 @@ def test_traffic_is_calibrated_on_the_finest_copies(tmp_path):
     assert k["forward"]["launches"] == 9
     assert k["forward"]["fetch_bytes_per_voxel"] == pytest.approx(61.0)
     assert k["forward"]["write_bytes_per_voxel"] == pytest.approx(16.0)
-    assert k["backward"]["launches"] == 6
-    assert k["backward"]["fetch_bytes_per_voxel"] == pytest.approx((4 * 50.0 + 2 * 30.0) / 6)
-    assert k["backward"]["write_bytes_per_voxel"] == pytest.approx((4 * 30.0 + 2 * 18.0) / 6)
+    # the backward class is the body-force step with a map: the map-only step and the
+    # coarse-level variant are left out
+    assert k["backward"]["launches"] == 4
+    assert k["backward"]["fetch_bytes_per_voxel"] == pytest.approx(50.0)
+    assert k["backward"]["write_bytes_per_voxel"] == pytest.approx(30.0)
     assert k["forward"]["mean_us_under_counters"] == pytest.approx((4 * 206.0 + 5 * 187.0) / 9)
 
 
@@ -100,3 +102,24 @@ def test_summary_names_and_levels(tmp_path):
     tags = {k[2] for k in out if k[0] == "void k_forward<1, false, false, false, true>"}
     assert tags == {""}                                            # one level per shape
     assert open(tmp_path / "s.txt").readline().startswith("# rocprofv3 summary of: cmd")
+
+
+def test_last_accepted_D_skips_rejected_and_stopped_rows():
+    import numpy as np
+    nan = float("nan")
+    tr = np.array([[3.0, 0.0, 3.0, 0.1, nan, nan, 1.0, 3.0],
+                   [2.0, 0.5, 1.5, 0.1, 0.9, nan, 1.0, 2.0],
+                   [2.5, 0.6, 1.9, 0.1, 0.9, nan, 0.0, 2.0],     # rejected trial
+                   [nan, nan, nan, 0.05, 0.9, nan, 0.0, 2.0]])   # stopped
+    assert bench.last_accepted_D(tr) == 1.5
+
+
+def test_kernel_names_follow_the_launch_choice():
+    assert bench.kernel_name("backward", {"staged_min_blocks": 2048}, False) == \
+        "k_backward_staged<1, true, false>"
+    assert bench.kernel_name("backward", {"staged_min_blocks": 1 << 30}, True) == \
+        "k_backward<1, true, false, true, true>"
+    assert bench.kernel_name("forward", {"fwd_tiles": 3584}, False) == \
+        "k_forward<1, false, false, false, true>"
+    assert bench.kernel_name("forward", {"fwd_tiles": 0}, False) == \
+        "k_forward<1, false, false, false, false>"

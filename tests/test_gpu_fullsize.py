@@ -14,9 +14,14 @@ The oracle cannot run whole registrations at this size in a test, so:
   time step of it, so the oracle run on a box with a wide enough margin gives
   the same values there;
 * the staged and the grid-stride backward sweeps (the choice only changes the
-  launch) give the same bits for the energy and the V-gradient.
+  launch) give the same bits for the energy and the V-gradient;
+* E, R, D, the image SSD and 100000 sampled entries of the V-gradient of one
+  velocity are compared with values the oracle computed on the whole grid
+  (tests/golden/make_atlas_gradient.py wrote them).
 """
 
+import importlib.util
+import os
 import sys
 
 import numpy as np
@@ -46,17 +51,7 @@ def say(msg):
 def _base_field(grid):
     """A smooth periodic field on a computational grid (physical units): a few low
     plane waves per component, at most 3 voxels per unit time (0.3 voxel per step)."""
-    rng = np.random.default_rng(77)
-    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64) / n for n in grid), indexing="ij",
-                          sparse=True)
-    out = np.zeros((3,) + grid, dtype=np.float64)
-    for c in range(3):
-        for _ in range(4):
-            k = rng.integers(1, 4, size=3)
-            ph = rng.uniform(0, 2 * np.pi)
-            out[c] += np.sin(2 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
-        out[c] *= 3.0 * H / np.abs(out[c]).max()
-    return out
+    return synth.plane_wave_velocity(grid, 77, 3.0 * H)
 
 
 PRM1 = L.Params(alpha=ALPHA, gamma=GAMMA, T=T, n_levels=1, iters=(0,))
@@ -144,3 +139,33 @@ def test_staged_and_grid_stride_sweeps_agree_bitwise(v_gpu, masks):
     np.testing.assert_array_equal(out["staged"][0], out["grid"][0])
     np.testing.assert_array_equal(out["staged"][1], out["grid"][1])
     assert np.isfinite(out["staged"][1][0])
+
+
+def _golden_script():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "make_atlas_gradient.py")
+    spec = importlib.util.spec_from_file_location("make_atlas_gradient", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_energy_and_gradient_against_stored_oracle(masks):
+    say("E, R, D and sampled V-gradient at the atlas size vs stored oracle values")
+    gs = _golden_script()
+    ref = np.load(gs.OUT)
+    v = gs.velocity()
+    assert v.shape[2:] == P1 and gs.T == T and gs.H == H
+    tt = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+    prm = L.Params(alpha=gs.ALPHA, gamma=gs.GAMMA, sigma=gs.SIGMA, T=T, n_levels=1, iters=(0,),
+                   weight=(1.0, 0.0))
+    g, out = L.lddmm_gradient(tt(masks.M0), tt(masks.M1), tt(masks.MI0), tt(masks.MI1), tt(v), prm,
+                              kind=L.GRAD_V, spacing=H)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for k, name in enumerate(("E", "R", "D", "img_ssd")):
+        assert abs(out[k] - float(ref[name])) <= 1e-5 * abs(float(ref[name])), name
+    idx = torch.as_tensor(ref["idx"].astype(np.int64), device=DEV)
+    got = g.reshape(-1)[idx].cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref["g"].astype(np.float64)).max() / float(ref["g_absmax"])
+    assert err < 2e-5, err
