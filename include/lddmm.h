@@ -48,6 +48,8 @@ extern "C" {
                                  alpha/gamma/sigma/spacing <= 0, workspace too small */
 #define LDDMM_EHIP       -2   /* HIP runtime or launch error */
 #define LDDMM_ENONFINITE -3   /* energy not finite (NaN/Inf velocity or inputs) */
+#define LDDMM_ESCRATCH   -4   /* lddmm_gradient_noalloc: the problem needs more than
+                                 LDDMM_SCRATCH_BYTES of workspace */
 #define LDDMM_WFOLD       1   /* warning: the returned v folds: min over j < T and the
                                  finest computational grid of det D(phi_{t_j,1}) <= 0
                                  (np.gradient stencil); result written */
@@ -173,6 +175,26 @@ int lddmm_energy(const lddmm_problem *p, const lddmm_params *params, double *out
  */
 int lddmm_gradient(const lddmm_problem *p, const lddmm_params *params, int32_t kind,
                    float *grad, double *out4, void *stream);
+
+/*
+ * lddmm_gradient without a caller workspace, for callers that cannot allocate
+ * device memory at all (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Arguments, results and errors are those of
+ * lddmm_gradient, except that p->workspace and p->workspace_bytes are ignored:
+ * the scratch is a static device array of LDDMM_SCRATCH_BYTES (256 MiB) in the
+ * library, one per GPU, held from the first use on that GPU until the process
+ * ends.  A problem whose workspace (lddmm_workspace_size with n_levels = 1, for
+ * its channel count) exceeds it returns LDDMM_ESCRATCH before any launch; 64^3
+ * with T = 10 and 80^3 with T = 4 fit.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU (two
+ * streams, or two host threads) race and give undefined results, so order them
+ * on one stream.  The first call on a GPU looks up the array's address
+ * (hipGetSymbolAddress) with that GPU current.  Async.
+ */
+#define LDDMM_SCRATCH_BYTES (256ull << 20)
+int lddmm_gradient_noalloc(const lddmm_problem *p, const lddmm_params *params, int32_t kind,
+                           float *grad, double *out4, void *stream);
 
 /*
  * Deform an image or a label map by a displacement (Methods, Postprocessing):

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -647,6 +648,34 @@ static int prepare(Ctx& c, const lddmm_problem* p, const lddmm_params* prm, int 
   return LDDMM_OK;
 }
 
+// ------------------------------------------------- static scratch ----
+// The workspace of lddmm_gradient_noalloc: one array per GPU, held from the
+// library's load on that GPU until the process ends.  In host code `scratch`
+// names a host-side stand-in, not device memory: only the address that
+// hipGetSymbolAddress returns for the current device may reach a kernel.
+constexpr size_t kScratchBytes = (size_t)LDDMM_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of the current GPU's scratch array, looked up once per device.
+static int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LDDMM_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LDDMM_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LDDMM_OK;
+}
+
+static int gradient_call(const lddmm_problem* p, const lddmm_params* prm, int32_t kind,
+                         float* grad, double* out4, void* stream);
+
 }  // namespace lddmm
 
 using namespace lddmm;
@@ -1046,6 +1075,31 @@ int lddmm_energy(const lddmm_problem* p, const lddmm_params* prm, double* out4, 
 
 int lddmm_gradient(const lddmm_problem* p, const lddmm_params* prm, int32_t kind, float* grad,
                    double* out4, void* stream) {
+  return gradient_call(p, prm, kind, grad, out4, stream);
+}
+
+int lddmm_gradient_noalloc(const lddmm_problem* p, const lddmm_params* prm, int32_t kind,
+                           float* grad, double* out4, void* stream) {
+  if (!p || !prm) return LDDMM_EINVAL;
+  Config cfg{};
+  int rc = make_config(&p->grid, prm, p->template_image != nullptr, 0, &cfg);
+  if (rc) return rc;
+  if (make_layout(cfg).total > kScratchBytes) return LDDMM_ESCRATCH;
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  lddmm_problem q = *p;
+  q.workspace = ws;
+  q.workspace_bytes = kScratchBytes;
+  return gradient_call(&q, prm, kind, grad, out4, stream);
+}
+
+}  // extern "C"
+
+namespace lddmm {
+
+static int gradient_call(const lddmm_problem* p, const lddmm_params* prm, int32_t kind,
+                         float* grad, double* out4, void* stream) {
   if (!grad || !out4) return LDDMM_EINVAL;
   if (kind != LDDMM_GRAD_V && kind != LDDMM_GRAD_L2) return LDDMM_EINVAL;
   if (kind == LDDMM_GRAD_L2 && prm && (prm->flags & LDDMM_FLAG_RK4)) return LDDMM_EINVAL;
@@ -1069,6 +1123,10 @@ int lddmm_gradient(const lddmm_problem* p, const lddmm_params* prm, int32_t kind
   backward_sweep(c, 0, p->v, p->v, p->v, true, UPD_WRITE_G, grad, -1, s);
   return hip_status();
 }
+
+}  // namespace lddmm
+
+extern "C" {
 
 int lddmm_apply(const lddmm_grid* grid, const float* u, const void* src, int32_t interp,
                 int32_t dtype, void* dst, void* stream) {
@@ -1228,6 +1286,8 @@ const char* lddmm_strerror(int code) {
     case LDDMM_ENONFINITE: return "energy is not finite";
     case LDDMM_WFOLD: return "warning: Jacobian determinant <= 0 (fold) seen";
     case LDDMM_WGUARD: return "warning: step guard stopped a level after repeated halvings";
+    case LDDMM_ESCRATCH:
+      return "problem needs more workspace than the static scratch of lddmm_gradient_noalloc";
     default: return "unknown status";
   }
 }

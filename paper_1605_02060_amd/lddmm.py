@@ -21,7 +21,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblddmm.so")
 
-OK, EINVAL, EHIP, ENONFINITE, WFOLD, WGUARD = 0, -1, -2, -3, 1, 2
+OK, EINVAL, EHIP, ENONFINITE, ESCRATCH, WFOLD, WGUARD = 0, -1, -2, -3, -4, 1, 2
 GRAD_V, GRAD_L2 = 0, 1
 INTERP_LINEAR, INTERP_NEAREST = 0, 1
 F32, I32 = 0, 1
@@ -93,6 +93,8 @@ def load():
     lib.lddmm_energy.restype = ctypes.c_int
     lib.lddmm_gradient.argtypes = [P(_Problem), P(_Params), i32, vp, vp, vp]
     lib.lddmm_gradient.restype = ctypes.c_int
+    lib.lddmm_gradient_noalloc.argtypes = [P(_Problem), P(_Params), i32, vp, vp, vp]
+    lib.lddmm_gradient_noalloc.restype = ctypes.c_int
     lib.lddmm_apply.argtypes = [P(_Grid), vp, vp, i32, i32, vp, vp]
     lib.lddmm_apply.restype = ctypes.c_int
     lib.lddmm_smooth_workspace_size.argtypes = [P(i32)]
@@ -140,7 +142,8 @@ def load():
 
 EXPORTED = ["lddmm_workspace_size", "lddmm_comp_grid", "lddmm_trace_rows", "lddmm_register",
             "lddmm_register_batched",
-            "lddmm_energy", "lddmm_gradient", "lddmm_apply", "lddmm_smooth_workspace_size",
+            "lddmm_energy", "lddmm_gradient", "lddmm_gradient_noalloc", "lddmm_apply",
+            "lddmm_smooth_workspace_size",
             "lddmm_smooth", "lddmm_make_mask", "lddmm_mask_image",
             "lddmm_histogram_match_workspace_size", "lddmm_histogram_match",
             "lddmm_align_workspace_size", "lddmm_align", "lddmm_apply_affine",
@@ -272,7 +275,7 @@ def _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10=None, phi01=None, trace=Non
         P = lddmm_comp_grid(N, params, 0, spacing)
         _expect(v, (params.T, 3) + P, torch.float32, "v")
         _expect(trace, (lddmm_trace_rows(params), TRACE_COLS), torch.float64, "trace")
-    if ws.dtype != torch.uint8 or ws.dim() != 1:
+    if ws is not None and (ws.dtype != torch.uint8 or ws.dim() != 1):
         raise ValueError("workspace: expected a 1-D uint8 tensor")
     pr = _Problem()
     pr.grid = _grid(M0.shape, spacing)
@@ -285,7 +288,7 @@ def _problem(M0, M1, MI0, MI1, v, spacing, ws, phi10=None, phi01=None, trace=Non
     pr.phi01 = _ptr(phi01)
     pr.trace = _ptr(trace)
     pr.workspace = _ptr(ws)
-    pr.workspace_bytes = ws.numel()
+    pr.workspace_bytes = ws.numel() if ws is not None else 0
     return pr
 
 
@@ -371,6 +374,24 @@ def lddmm_gradient(M0, M1, MI0, MI1, v, params: Params, kind=GRAD_V, spacing=1.0
     pr = _problem(M0, M1, MI0, MI1, v, spacing, ws, params=_single_level(params))
     _check(load().lddmm_gradient(ctypes.byref(pr), ctypes.byref(params.c()), int(kind),
                                  _ptr(grad), _ptr(out), _stream(stream)), "lddmm_gradient")
+    return grad, out
+
+
+def lddmm_gradient_noalloc(M0, M1, MI0, MI1, v, params: Params, kind=GRAD_V, spacing=1.0,
+                           grad=None, out=None, stream=None):
+    """lddmm_gradient with the library's static scratch instead of a workspace (no
+    device allocation in the library).  grad / out may be passed in, so that the
+    call itself allocates nothing either; returns (grad, out4)."""
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=M0.device)
+    if grad is None:
+        grad = torch.empty_like(v)
+    _expect(grad, tuple(v.shape), torch.float32, "grad")
+    _expect(out, (4,), torch.float64, "out")
+    pr = _problem(M0, M1, MI0, MI1, v, spacing, None, params=_single_level(params))
+    _check(load().lddmm_gradient_noalloc(ctypes.byref(pr), ctypes.byref(params.c()), int(kind),
+                                         _ptr(grad), _ptr(out), _stream(stream)),
+           "lddmm_gradient_noalloc")
     return grad, out
 
 
