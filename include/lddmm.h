@@ -158,7 +158,9 @@ int lddmm_register_batched(lddmm_problem *p, int32_t n, const lddmm_params *para
                            int32_t *status, void *stream);
 
 /*
- * Energy of p->v on the single-level grid (n_levels ignored; h = grid.spacing):
+ * Energy of p->v (Methods, Registration: the objective E(v) = int ||L v_t||^2 dt +
+ * sigma^-2 ||J0 o phi_10 - J1||^2, with the Mask-LDDMM channels of Methods,
+ * Preprocessing) on the single-level grid (n_levels ignored; h = grid.spacing):
  * out4 (device, 4 doubles) = {E, R, D, image SSD}, with
  *   R = dt h^3 sum_j sum_x |L v_j|^2 (periodic 7-point Laplacian),
  *   D = h^3/sigma^2 sum_c w_c sum_x (J0c o phi_10 - J1c)^2,
@@ -168,8 +170,12 @@ int lddmm_energy(const lddmm_problem *p, const lddmm_params *params, double *out
                  void *stream);
 
 /*
- * Gradient of E at p->v (single level): kind LDDMM_GRAD_V writes Beg's
- * V-gradient 2 v_j - K b_j; kind LDDMM_GRAD_L2 writes the exact derivative of
+ * Gradient of E at p->v (Methods, Registration: the gradient that the paper's
+ * gradient descent follows, after Beg et al. 2005, which it cites), single
+ * level: kind LDDMM_GRAD_V writes Beg's V-gradient
+ *   g_j = 2 v_j - K b_j,
+ *   b_j = (2/sigma^2) det(D phi_{t_j,1}) sum_c w_c (r_c o phi_{t_j,1}) grad(J0c o phi_{t_j,0}),
+ * r_c = J0c o phi_10 - J1c; kind LDDMM_GRAD_L2 writes the exact derivative of
  * the discrete energy (reverse mode through the semi-Lagrangian sweep, with the
  * adjoint of trilinear sampling).  grad is [T][3][P]; out4 as lddmm_energy.  Async.
  */
@@ -200,7 +206,11 @@ int lddmm_gradient_noalloc(const lddmm_problem *p, const lddmm_params *params, i
  * Deform an image or a label map by a displacement (Methods, Postprocessing):
  *   dst(x) = src(x + u(x)/h), u [3][N] in physical units, h = grid->spacing.
  * LINEAR: trilinear, zero outside (dtype must be LDDMM_F32).
- * NEAREST: src[floor(y + 1/2)], zero outside (LDDMM_F32 or LDDMM_I32 labels).  Async.
+ * NEAREST: src[floor(y + 1/2)], zero outside (LDDMM_F32 or LDDMM_I32 labels); the
+ * rounding is decided in FP32 from the displacement alone: index i +
+ * floor(u * (1/h) + 1/2) per axis, with 1/h rounded to FP32 once, so a position
+ * within FP32 rounding of a half-integer can round either way against an FP64
+ * evaluation of the same formula.  Async.
  */
 int lddmm_apply(const lddmm_grid *grid, const float *u, const void *src, int32_t interp,
                 int32_t dtype, void *dst, void *stream);

@@ -260,7 +260,11 @@ def splat_clamp(w, pos, shape):
 
 
 def sample_nearest(f, pos):
-    """Nearest-neighbour sample f[floor(y + 1/2)], zero outside (label transfer)."""
+    """Nearest-neighbour sample f[floor(y + 1/2)], zero outside (label transfer).
+
+    The rounding is evaluated in FP64 here.  The library takes the same decision
+    in FP32 (apply_nearest_f32 below), so the two differ only where a position
+    lies within FP32 rounding of a half-integer."""
     nz, ny, nx = f.shape
     n = (nx, ny, nz)
     idx = [np.floor(pos[c] + 0.5).astype(np.int64) for c in range(3)]
@@ -740,3 +744,27 @@ def apply_warp(u, src, h=1.0, interp="linear"):
     if interp == "linear":
         return sample_zero(np.asarray(src, np.float64), pos)
     return sample_nearest(np.asarray(src), pos)
+
+
+def apply_nearest_f32(u, src, h=1.0):
+    """Label transfer with the rounding decided in FP32, as the library decides it
+    (reading: the paper names nearest-neighbour interpolation, Methods,
+    Postprocessing, but no tie rule or precision): per axis the index is
+    i + floor(u * (1/h) + 1/2), every operation in float32, with 1/h rounded to
+    float32 once; zero outside the grid.  An integer decided by floating point:
+    both sides take the decision in the kernel's precision."""
+    src = np.asarray(src)
+    u = np.asarray(u, np.float32)
+    inv_h = np.float32(1.0 / h)
+    nz, ny, nx = src.shape
+    n = (nx, ny, nz)
+    X = index_positions(src.shape).astype(np.int64)
+    idx = []
+    for c in range(3):
+        d = u[c] * inv_h + np.float32(0.5)                 # float32 multiply and add
+        idx.append(X[c] + np.floor(d).astype(np.int64))
+    ok = np.ones(src.shape, dtype=bool)
+    for c in range(3):
+        ok &= (idx[c] >= 0) & (idx[c] < n[c])
+    val = src[np.clip(idx[2], 0, nz - 1), np.clip(idx[1], 0, ny - 1), np.clip(idx[0], 0, nx - 1)]
+    return np.where(ok, val, np.zeros((), dtype=src.dtype))

@@ -34,9 +34,10 @@ def common_flags():
 
 
 # Sources whose kernels compute the same step in two implementations (the sweeps:
-# grid-stride and LDS-staged): multiply-add fusion only within one source
-# expression, so both give the same bits.
-CONTRACT_ON = {"flow.hip"}
+# grid-stride and LDS-staged; the FFT passes: single and batched launches of one
+# line transform): multiply-add fusion only within one source expression, so
+# both give the same bits.
+CONTRACT_ON = {"flow.hip", "fft.hip"}
 # Sources whose FP64 arithmetic restates a definition operation by operation
 # (histogram quantiles and the intensity map; affine sampling positions, where
 # a whole-number position must stay whole): no multiply-add fusion at all.
@@ -72,6 +73,40 @@ def build(verbose=True) -> str:
     if verbose:
         print(f"built {LIB}")
     return LIB
+
+
+def build_host_asan(out_dir, driver, verbose=False) -> str:
+    """Build an executable from `driver` (C++) and every source, with
+    AddressSanitizer on the host code only (the device code is built as usual,
+    so that the objects carry their kernels), to check the host runtime
+    (argument validation, geometry, workspace layout) on the CPU.  The driver may
+    only call paths that return before any device work.  Returns the
+    executable's path."""
+    os.makedirs(out_dir, exist_ok=True)
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", "-fno-omit-frame-pointer", "-I", CSRC, "-I",
+             INCLUDE, "-Wno-unused-command-line-argument", "-Wno-unused-result",
+             "-Xarch_host", "-fsanitize=address"]
+
+    def host_obj(src):
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".asan.o")
+        cmd = [hipcc(), f"--offload-arch={ARCH}", *flags, "-Xclang", "-target-feature",
+               "-Xclang", "-packed-fp32-ops", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed for {src}:\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(host_obj, SOURCES))
+    exe = os.path.join(out_dir, "host_abi_checks")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", *flags, "-x", "c++", driver, "-x", "none", *objs,
+           "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"host link failed:\n{r.stderr}")
+    if verbose:
+        print(f"built {exe}")
+    return exe
 
 
 if __name__ == "__main__":

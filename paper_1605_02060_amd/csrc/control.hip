@@ -26,24 +26,30 @@ void launch_level_begin(State* st, double step, int keep_flags, hipStream_t s) {
   hipLaunchKernelGGL(k_level_begin, dim3(1), dim3(64), 0, s, st, step, keep_flags);
 }
 
-// Fixed-order sum of `count` partials by one 1024-thread block.
-__device__ double block1024_sum(const double* p, int count, double* red) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) v += p[i];
-  red[threadIdx.x] = v;
+// Three sums over one 1024-thread block at once (per-thread values in, totals out
+// in every thread); red holds 3 x 1024 doubles.
+__device__ void block1024_sum3(double& a, double& b, double& c, double* red) {
+  const int t = threadIdx.x, n = blockDim.x;
+  red[t] = a;
+  red[n + t] = b;
+  red[2 * n + t] = c;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int s = n / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red[t] += red[t + s];
+      red[n + t] += red[n + t + s];
+      red[2 * n + t] += red[2 * n + t + s];
+    }
     __syncthreads();
   }
-  const double r = red[0];
+  a = red[0];
+  b = red[n];
+  c = red[2 * n];
   __syncthreads();
-  return r;
 }
 
-__device__ double block1024_min(const double* p, int count, double* red) {
-  double v = 1e300;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) v = fmin(v, p[i]);
+// Minimum of one value per thread over a 1024-thread block.
+__device__ double block1024_min_of(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -55,6 +61,12 @@ __device__ double block1024_min(const double* p, int count, double* red) {
   return r;
 }
 
+__device__ double block1024_min(const double* p, int count, double* red) {
+  double v = 1e300;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) v = fmin(v, p[i]);
+  return block1024_min_of(v, red);
+}
+
 // Reduce the energy of the evaluated velocity and take the guard decision.
 //  init = 1 : first evaluation of a level (row 0), no decision.
 //  mode GRAD / RETRY : the slot evaluated a trial in buffer 1 - base.
@@ -63,7 +75,7 @@ __device__ __forceinline__ void decide_body(State* st, const double* partR, int 
                                             const double* partDet, int nfw, int nbw, int has_img,
                                             double dt, double h3, double inv_sigma2, int guard,
                                             double* trace, int init) {
-  __shared__ double red[1024];
+  __shared__ double red[3 * 1024];
   const int mode = st->mode;
   if (mode == MODE_STOPPED) {
     if (threadIdx.x == 0 && !init) {
@@ -81,15 +93,32 @@ __device__ __forceinline__ void decide_body(State* st, const double* partR, int 
     }
     return;
   }
-  double R = 0.0;
-  for (int j = 0; j < T; ++j) R += block1024_sum(partR + (long long)j * kPartMax, nfw, red);
-  const double D = block1024_sum(partD, nfw, red);
-  const double I = block1024_sum(partI, nfw, red);
+  // one strided pass over the partials of every time step, then one reduction tree
+  // per quantity (the order is fixed, so repeated calls give the same bits)
+  double R, D, I;
+  {
+    double r = 0.0, d = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < T * nfw; i += blockDim.x) {
+      const int j = i / nfw;
+      r += partR[(long long)j * kPartMax + (i - j * nfw)];
+    }
+    for (int i = threadIdx.x; i < nfw; i += blockDim.x) {
+      d += partD[i];
+      im += partI[i];
+    }
+    block1024_sum3(r, d, im, red);
+    R = r;
+    D = d;
+    I = im;
+  }
   double md = 0.0;
   if (!init && mode == MODE_GRAD) {
-    md = 1e300;
-    for (int j = 0; j < T; ++j)
-      md = fmin(md, block1024_min(partDet + (long long)j * kPartMax, nbw, red));
+    double m = 1e300;
+    for (int i = threadIdx.x; i < T * nbw; i += blockDim.x) {
+      const int j = i / nbw;
+      m = fmin(m, partDet[(long long)j * kPartMax + (i - j * nbw)]);
+    }
+    md = block1024_min_of(m, red);
   }
   if (threadIdx.x != 0) return;
   const double nan = __longlong_as_double(0x7ff8000000000000LL);

@@ -15,6 +15,7 @@
 // into the K_hat multiply.  Twiddles and the Laplacian symbol are generated in
 // FP64 on the device and rounded once.
 #include "device.h"
+#include "dft.h"
 
 namespace lddmm {
 
@@ -336,6 +337,572 @@ __device__ __forceinline__ const float2* stage_twiddles(float2* sm, int tile_ele
   return t;
 }
 
+// ------------------------------------ y and z passes, compile-time plans ----
+// A line of length N = N1 N2 is transformed by G = max(N1, N2) threads in two
+// steps with one exchange through LDS:
+//   x[n1 + N1 n2] --(N2-point DFT over n2, thread n1)--> Y[n1][k2]
+//   --(times W_N^(n1 k2))--> --(N1-point DFT over n1, thread k2)--> X[k2 + N2 k1].
+// A tile is kCT consecutive kx columns of one (component, plane); thread
+// (c, t) = (tid mod kCT, tid / kCT), so the kCT lanes of a row move one
+// 128-byte segment.  Each thread loads its N2 values straight from global
+// memory and stores its N1 results there; only the exchange goes through LDS
+// (line stride N + 1).  The z pass keeps the spectrum in registers between the
+// forward transform, the K multiply and the inverse transform; the inverse runs
+// the same split the other way round (k2 + N2 k1 -> p1 + N1 p2), which takes the
+// forward output order as it is and returns natural order.
+// Every index is a compile-time constant or a per-thread offset, so the stages
+// spend their instructions on the butterflies.  Lengths without a plan use the
+// runtime-planned passes above.
+
+constexpr int kCT = 16;   // kx columns per tile of a compile-time pass
+
+#define LDDMM_CT_PLANS(X) \
+  X(240, 16, 15) X(160, 16, 10) X(120, 12, 10) X(80, 10, 8) X(60, 10, 6) X(40, 8, 5) \
+  X(32, 8, 4) X(64, 8, 8) X(96, 12, 8) X(128, 16, 8) X(70, 10, 7) X(140, 14, 10)
+
+static bool ct_plan(int n, int* n1, int* n2) {
+#define LDDMM_CT_CASE(N, A, B) \
+  if (n == N) {                \
+    *n1 = A;                   \
+    *n2 = B;                   \
+    return true;               \
+  }
+  LDDMM_CT_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+  return false;
+}
+
+// LDS of one compile-time tile: the exchange, the twiddles and (z pass) the
+// K symbol tables.
+static size_t ct_lds_bytes(int n) {
+  return sizeof(float2) * ((size_t)kCT * (n + 1) + n) + sizeof(float) * ((size_t)n + kCT);
+}
+
+// y pass (forward, or inverse through conj(DFT(conj X))) of columns
+// bx * kCT .. + kCT - 1 of plane z of component comp.
+template <int N1, int N2, bool INV>
+__device__ __forceinline__ void ct_y_body(const FftPair& f, int bx, int zslab, int comp) {
+  constexpr int N = N1 * N2, LS = N + 1;
+  extern __shared__ float2 sm[];
+  float2* sx = sm;
+  float2* stw = sm + kCT * LS;
+  const Geom& g = f.g;
+  const int hs = g.hs;
+  const int c = threadIdx.x % kCT, t = threadIdx.x / kCT;
+  float2* __restrict__ col =
+      f.S + (long long)comp * g.nspec + (long long)zslab * g.ny * hs + bx * kCT + c;
+  const float2* __restrict__ tw = f.tw[1];
+  for (int e = threadIdx.x; e < N; e += blockDim.x) stw[e] = tw[e];
+  float2 v[N2];
+  if (t < N1) {
+#pragma unroll
+    for (int q = 0; q < N2; ++q) {
+      const float2 a = col[(t + N1 * q) * hs];
+      v[q] = INV ? dft::conj(a) : a;
+    }
+  }
+  __syncthreads();
+  if (t < N1) {
+    dft::dft<N2>(v);
+#pragma unroll
+    for (int q = 1; q < N2; ++q) v[q] = dft::mul(v[q], stw[t * q]);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) sx[c * LS + t + N1 * q] = v[q];
+  }
+  __syncthreads();
+  if (t < N2) {
+    float2 w[N1];
+#pragma unroll
+    for (int p = 0; p < N1; ++p) w[p] = sx[c * LS + p + N1 * t];
+    dft::dft<N1>(w);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) col[(t + N2 * k) * hs] = INV ? dft::conj(w[k]) : w[k];
+  }
+}
+
+// z pass: forward transform, K_hat / |P| (and conj), forward transform of the
+// conjugate, conj on the way out: N_z IDFT_z(K_hat X / |P|).
+template <int N1, int N2>
+__device__ __forceinline__ void ct_zK_body(const FftPair& f, int bx, int ky, int comp) {
+  constexpr int N = N1 * N2, LS = N + 1;
+  extern __shared__ float2 sm[];
+  float2* sx = sm;
+  float2* stw = sm + kCT * LS;
+  float* saz = reinterpret_cast<float*>(stw + N);
+  float* scxy = saz + N;
+  const Geom& g = f.g;
+  const int hs = g.hs;
+  const int zs = g.ny * hs;
+  const int c = threadIdx.x % kCT, t = threadIdx.x / kCT;
+  float2* __restrict__ col = f.S + (long long)comp * g.nspec + (long long)ky * hs + bx * kCT + c;
+  const float2* __restrict__ tw = f.tw[2];
+  const double* __restrict__ lamz = f.lam[2];
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    stw[e] = tw[e];
+    saz[e] = (float)(f.alpha * lamz[e]);
+  }
+  if (threadIdx.x < kCT) {
+    const int kx = bx * kCT + (int)threadIdx.x;
+    scxy[threadIdx.x] = (float)(f.gamma + f.alpha * (f.lam[0][kx < g.hx ? kx : 0] + f.lam[1][ky]));
+  }
+  float2 v[N2];
+  if (t < N1) {
+#pragma unroll
+    for (int q = 0; q < N2; ++q) v[q] = col[(t + N1 * q) * zs];
+  }
+  __syncthreads();
+  if (t < N1) {
+    dft::dft<N2>(v);
+#pragma unroll
+    for (int q = 1; q < N2; ++q) v[q] = dft::mul(v[q], stw[t * q]);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) sx[c * LS + t + N1 * q] = v[q];
+  }
+  __syncthreads();
+  float2 w[N1];
+  if (t < N2) {
+#pragma unroll
+    for (int p = 0; p < N1; ++p) w[p] = sx[c * LS + p + N1 * t];
+    dft::dft<N1>(w);
+    const float inv_n = (float)(1.0 / ((double)g.nx * (double)g.ny * (double)g.nz));
+    const float cxy = scxy[c];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const float d = cxy + saz[t + N2 * k];
+      const float kh = inv_n * __builtin_amdgcn_rcpf(d * d);
+      w[k] = make_float2(w[k].x * kh, -w[k].y * kh);          // conj(K_hat X / |P|)
+    }
+    dft::dft<N1>(w);
+#pragma unroll
+    for (int p = 1; p < N1; ++p) w[p] = dft::mul(w[p], stw[t * p]);
+  }
+  __syncthreads();
+  if (t < N2) {
+#pragma unroll
+    for (int p = 0; p < N1; ++p) sx[c * LS + t + N2 * p] = w[p];
+  }
+  __syncthreads();
+  if (t < N1) {
+    float2 u[N2];
+#pragma unroll
+    for (int q = 0; q < N2; ++q) u[q] = sx[c * LS + q + N2 * t];
+    dft::dft<N2>(u);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) col[(t + N1 * q) * zs] = dft::conj(u[q]);
+  }
+}
+
+template <int N1, int N2, bool INV>
+__global__ __launch_bounds__(kCT * (N1 > N2 ? N1 : N2)) void k_fftc_y(FftPair f) {
+  if (!gate(f.st, f.need_mode)) return;
+  ct_y_body<N1, N2, INV>(f, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// XCD-aware tile order as in k_fft_z_K.
+template <int N1, int N2>
+__global__ __launch_bounds__(kCT * (N1 > N2 ? N1 : N2)) void k_fftc_zK(FftPair f) {
+  if (!gate(f.st, f.need_mode)) return;
+  const uint32_t total = gridDim.x;
+  uint32_t t = blockIdx.x;
+  if ((total % kXCD) == 0) t = (t % kXCD) * (total / kXCD) + t / kXCD;
+  const int bx = (int)(t % (uint32_t)f.nbx_z), r = (int)(t / (uint32_t)f.nbx_z);
+  ct_zK_body<N1, N2>(f, bx, r % f.g.ny, r / f.g.ny);
+}
+
+// The compile-time body for this problem's length, if it has one (batched
+// launches: 256 threads, kCT x 16, of which the plan uses kCT x G).
+template <bool INV>
+__device__ __forceinline__ bool ct_y_dispatch(const FftPair& f, int bx, int zslab, int comp) {
+  switch (f.g.ny) {
+#define LDDMM_CT_CASE(N, A, B)              \
+  case N:                                   \
+    ct_y_body<A, B, INV>(f, bx, zslab, comp); \
+    return true;
+    LDDMM_CT_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      return false;
+  }
+}
+
+__device__ __forceinline__ bool ct_zK_dispatch(const FftPair& f, int bx, int ky, int comp) {
+  switch (f.g.nz) {
+#define LDDMM_CT_CASE(N, A, B)          \
+  case N:                               \
+    ct_zK_body<A, B>(f, bx, ky, comp); \
+    return true;
+    LDDMM_CT_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      return false;
+  }
+}
+
+// ------------------------------------------- x passes, compile-time plans ----
+// Rows are packed two by two into complex lines as in the runtime-planned x
+// passes (3 lines per row pair: bx and by of each row, bz of both).  A block
+// holds kXP(G) row pairs, 3 kXP lines of length N = N1 N2, one line per G
+// threads.  Loads and stores stay row-contiguous through LDS (line stride N + 1);
+// the two factor steps run in registers between them: step A in place (a thread
+// reads and writes the same positions), step B through registers.
+
+#define LDDMM_CTX_PLANS(X) LDDMM_CT_PLANS(X) X(280, 20, 14)
+
+// Row pairs per block of a compile-time x pass: as many as fit 256 threads.
+__host__ __device__ constexpr int kXP(int G) { return kBlock / (3 * G); }
+
+static bool ctx_plan(int n, int* n1, int* n2) {
+#define LDDMM_CT_CASE(N, A, B) \
+  if (n == N) {                \
+    *n1 = A;                   \
+    *n2 = B;                   \
+    return true;               \
+  }
+  LDDMM_CTX_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+  return false;
+}
+
+// In-LDS transform of the block's lines: natural order in sx[l LS + x] and out.
+template <int N1, int N2, int LPB>
+__device__ __forceinline__ void ct_lines(float2* sx, const float2* stw) {
+  constexpr int N = N1 * N2, G = N1 > N2 ? N1 : N2, LS = N + 1;
+  const int l = threadIdx.x / G, t = threadIdx.x % G;
+  if (l < LPB && t < N1) {
+    float2 v[N2];
+#pragma unroll
+    for (int q = 0; q < N2; ++q) v[q] = sx[l * LS + t + N1 * q];
+    dft::dft<N2>(v);
+#pragma unroll
+    for (int q = 1; q < N2; ++q) v[q] = dft::mul(v[q], stw[t * q]);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) sx[l * LS + t + N1 * q] = v[q];
+  }
+  __syncthreads();
+  float2 w[N1];
+  if (l < LPB && t < N2) {
+#pragma unroll
+    for (int p = 0; p < N1; ++p) w[p] = sx[l * LS + p + N1 * t];
+    dft::dft<N1>(w);
+  }
+  __syncthreads();
+  if (l < LPB && t < N2) {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) sx[l * LS + t + N2 * k] = w[k];
+  }
+  __syncthreads();
+}
+
+// 16-byte global accesses of the x passes when rows allow them: a row of N floats
+// (and each component plane) starts on a 16-byte boundary when 4 divides N.
+template <int N>
+struct XVec {
+  static constexpr bool on = (N % 4) == 0;
+};
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
+template <int N1, int N2>
+__device__ __forceinline__ void ctx_fwd_body(const FftPair& f, int block) {
+  constexpr int N = N1 * N2, G = N1 > N2 ? N1 : N2, LS = N + 1, HX = N / 2 + 1;
+  constexpr int PPB = kXP(G), LPB = 3 * PPB;
+  extern __shared__ float2 sm[];
+  float2* sx = sm;
+  float2* stw = sm + LPB * LS;
+  const float* __restrict__ b = f.b;
+  float2* __restrict__ S = f.S;
+  const Geom& g = f.g;
+  const long long n = g.n;
+  const int nrows = g.ny * g.nz, hs = g.hs;
+  const int pair0 = block * PPB;
+  const float2* __restrict__ tw = f.tw[0];
+  for (int e = threadIdx.x; e < N; e += blockDim.x) stw[e] = tw[e];
+  // line l of the block: which = l mod 3 picks (bx, by) of row r0, of row r1, or bz of both
+  auto row_src = [&](int l, const float*& pa, const float*& pb) {
+    const int pp = l / 3, which = l - 3 * pp;
+    const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
+    pa = pb = nullptr;
+    if (which == 0) {
+      if (r0 < nrows) { pa = b + (long long)r0 * N; pb = b + n + (long long)r0 * N; }
+    } else if (which == 1) {
+      if (r1 < nrows) { pa = b + (long long)r1 * N; pb = b + n + (long long)r1 * N; }
+    } else {
+      if (r0 < nrows) pa = b + 2 * n + (long long)r0 * N;
+      if (r1 < nrows) pb = b + 2 * n + (long long)r1 * N;
+    }
+  };
+  if constexpr (XVec<N>::on) {
+    constexpr int N4 = N / 4;
+    constexpr int PER = (LPB * N4 + 3 * PPB * G - 1) / (3 * PPB * G);
+    float4 ta[PER], tb[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * blockDim.x;
+      ta[r] = tb[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < LPB * N4) {
+        const int l = e / N4, x4 = e - l * N4;
+        const float *pa, *pb;
+        row_src(l, pa, pb);
+        if (pa) ta[r] = ld4(pa + 4 * x4);
+        if (pb) tb[r] = ld4(pb + 4 * x4);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * blockDim.x;
+      if (e < LPB * N4) {
+        const int l = e / N4, x = 4 * (e - l * N4);
+        float2* d = sx + l * LS + x;
+        d[0] = make_float2(ta[r].x, tb[r].x);
+        d[1] = make_float2(ta[r].y, tb[r].y);
+        d[2] = make_float2(ta[r].z, tb[r].z);
+        d[3] = make_float2(ta[r].w, tb[r].w);
+      }
+    }
+  } else {
+    constexpr int PER = (LPB * N + 3 * PPB * G - 1) / (3 * PPB * G);
+    float2 tmp[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * blockDim.x;
+      float2 z = make_float2(0.f, 0.f);
+      if (e < LPB * N) {
+        const int l = e / N, x = e - l * N;
+        const float *pa, *pb;
+        row_src(l, pa, pb);
+        z = make_float2(pa ? pa[x] : 0.f, pb ? pb[x] : 0.f);
+      }
+      tmp[r] = z;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * blockDim.x;
+      if (e < LPB * N) {
+        const int l = e / N, x = e - l * N;
+        sx[l * LS + x] = tmp[r];
+      }
+    }
+  }
+  __syncthreads();
+  ct_lines<N1, N2, LPB>(sx, stw);
+  // Hermitian split: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / 2i.
+  // With 16-byte stores each thread writes k and k + 1; the pair past HX - 1 lands
+  // in the row's padding (hs > HX), which no pass reads.
+  auto split = [&](int l, int k, float2& A, float2& B) {
+    const float2 zk = sx[l * LS + k];
+    const float2 zm = dft::conj(sx[l * LS + (k == 0 ? 0 : N - k)]);
+    A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    B = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));
+  };
+  constexpr int KV = XVec<N>::on ? 2 : 1;              // spectrum entries per store
+  constexpr int HK = (HX + KV - 1) / KV;
+  for (int e = threadIdx.x; e < LPB * HK; e += blockDim.x) {
+    const int l = e / HK, k = KV * (e - l * HK);
+    const int pp = l / 3, which = l - 3 * pp;
+    const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
+    float2 A0, B0, A1, B1;
+    split(l, k, A0, B0);
+    if (KV == 2) split(l, k + 1, A1, B1);
+    auto put = [&](long long at, float2 x0, float2 x1) {
+      if (KV == 2)
+        *reinterpret_cast<float4*>(S + at) = make_float4(x0.x, x0.y, x1.x, x1.y);
+      else
+        S[at] = x0;
+    };
+    if (which == 0) {
+      if (r0 < nrows) {
+        put((long long)r0 * hs + k, A0, A1);
+        put(g.nspec + (long long)r0 * hs + k, B0, B1);
+      }
+    } else if (which == 1) {
+      if (r1 < nrows) {
+        put((long long)r1 * hs + k, A0, A1);
+        put(g.nspec + (long long)r1 * hs + k, B0, B1);
+      }
+    } else {
+      if (r0 < nrows) put(2 * g.nspec + (long long)r0 * hs + k, A0, A1);
+      if (r1 < nrows) put(2 * g.nspec + (long long)r1 * hs + k, B0, B1);
+    }
+  }
+}
+
+template <int N1, int N2>
+__device__ __forceinline__ void ctx_inv_body(const FftPair& f, const UpdArgs& u, int block) {
+  constexpr int N = N1 * N2, G = N1 > N2 ? N1 : N2, LS = N + 1, HX = N / 2 + 1;
+  constexpr int PPB = kXP(G), LPB = 3 * PPB;
+  constexpr bool V = XVec<N>::on;
+  const State* st = u.st;
+  extern __shared__ float2 sm[];
+  float2* sx = sm;
+  float2* stw = sm + LPB * LS;
+  const float2* __restrict__ S = f.S;
+  const Geom& g = f.g;
+  const long long n = g.n;
+  const int nrows = g.ny * g.nz, hs = g.hs;
+  const int pair0 = block * PPB;
+  const float2* __restrict__ tw = f.tw[0];
+  for (int e = threadIdx.x; e < N; e += blockDim.x) stw[e] = tw[e];
+  // Each half-spectrum value is read once and written to k and to its mirror N - k,
+  // as conj(Z) with Z = A + i B for the forward transform of the inverse; the upper
+  // half holds Z[N - k] = conj A[k] + i conj B[k].  With 16-byte loads a thread takes
+  // k and k + 1 (the entry past HX - 1 is row padding and is dropped).
+  constexpr int KV = V ? 2 : 1;
+  constexpr int HK = (HX + KV - 1) / KV;
+  constexpr int PER = (LPB * HK + 3 * PPB * G - 1) / (3 * PPB * G);
+  float4 tA[PER], tB[PER];          // (A_k, A_k+1), (B_k, B_k+1); .zw unused when KV = 1
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * blockDim.x;
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+    if (e < LPB * HK) {
+      const int l = e / HK, k = KV * (e - l * HK);
+      const int pp = l / 3, which = l - 3 * pp;
+      const int r0 = 2 * (pair0 + pp), r1 = r0 + 1;
+      auto get = [&](long long at) {
+        if (V) return *reinterpret_cast<const float4*>(S + at);
+        const float2 z = S[at];
+        return make_float4(z.x, z.y, 0.f, 0.f);
+      };
+      if (which == 0) {
+        if (r0 < nrows) {
+          A = get((long long)r0 * hs + k);
+          B = get(g.nspec + (long long)r0 * hs + k);
+        }
+      } else if (which == 1) {
+        if (r1 < nrows) {
+          A = get((long long)r1 * hs + k);
+          B = get(g.nspec + (long long)r1 * hs + k);
+        }
+      } else {
+        if (r0 < nrows) A = get(2 * g.nspec + (long long)r0 * hs + k);
+        if (r1 < nrows) B = get(2 * g.nspec + (long long)r1 * hs + k);
+      }
+    }
+    tA[r] = A;
+    tB[r] = B;
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = threadIdx.x + r * blockDim.x;
+    if (e < LPB * HK) {
+      const int l = e / HK, k0 = KV * (e - l * HK);
+#pragma unroll
+      for (int q = 0; q < KV; ++q) {
+        const int k = k0 + q;
+        if (k >= HX) continue;
+        const float2 A = q ? make_float2(tA[r].z, tA[r].w) : make_float2(tA[r].x, tA[r].y);
+        const float2 B = q ? make_float2(tB[r].z, tB[r].w) : make_float2(tB[r].x, tB[r].y);
+        sx[l * LS + k] = make_float2(A.x - B.y, -(A.y + B.x));
+        if (k >= 1 && N - k >= HX) sx[l * LS + N - k] = make_float2(A.x + B.y, A.y - B.x);
+      }
+    }
+  }
+  __syncthreads();
+  ct_lines<N1, N2, LPB>(sx, stw);
+  // result z = conj(DFT(conj Z)): real line a = Re z = Re y, b = Im z = -Im y
+  float* vA = u.vA;
+  float* vB = u.vB;
+  const int base = st->base;
+  const float eps = (float)st->eps;
+  constexpr int XV = V ? 4 : 1;                  // voxels per thread and row
+  constexpr int NX = N / XV;
+  for (int e = threadIdx.x; e < 2 * PPB * NX; e += blockDim.x) {
+    const int q = e / NX, x = XV * (e - q * NX);
+    const int pp = q >> 1, half = q & 1;
+    const int row = 2 * (pair0 + pp) + half;
+    if (row >= nrows) continue;
+    float kb0[XV], kb1[XV], kb2[XV];
+#pragma unroll
+    for (int m = 0; m < XV; ++m) {
+      const float2 y01 = sx[(3 * pp + half) * LS + x + m];
+      const float2 y2 = sx[(3 * pp + 2) * LS + x + m];
+      kb0[m] = y01.x;
+      kb1[m] = -y01.y;
+      kb2[m] = half ? -y2.y : y2.x;
+    }
+    const long long i = (long long)row * N + x;
+    if (u.kind == UPD_WRITE_KB) {
+#pragma unroll
+      for (int m = 0; m < XV; ++m) {
+        u.out[i + m] = kb0[m];
+        u.out[i + n + m] = kb1[m];
+        u.out[i + 2 * n + m] = kb2[m];
+      }
+    } else if (u.kind == UPD_WRITE_G) {
+      const float* v = (u.vfix ? u.vfix : (base ? vB : vA)) + (long long)u.j * 3 * n;
+      float* o = u.out + (long long)u.j * 3 * n;
+#pragma unroll
+      for (int m = 0; m < XV; ++m) {
+        o[i + m] = 2.f * v[i + m] - kb0[m];
+        o[i + n + m] = 2.f * v[i + n + m] - kb1[m];
+        o[i + 2 * n + m] = 2.f * v[i + 2 * n + m] - kb2[m];
+      }
+    } else {
+      const float* v = (base ? vB : vA) + (long long)u.j * 3 * n;
+      float* vt = (base ? vA : vB) + (long long)u.j * 3 * n;
+      if (V) {
+        const float4 a0 = ld4(v + i), a1 = ld4(v + i + n), a2 = ld4(v + i + 2 * n);
+        auto upd = [&](float4 a, const float* kb) {
+          return make_float4(a.x - eps * (2.f * a.x - kb[0]), a.y - eps * (2.f * a.y - kb[1]),
+                             a.z - eps * (2.f * a.z - kb[2]), a.w - eps * (2.f * a.w - kb[3]));
+        };
+        st4(vt + i, upd(a0, kb0));
+        st4(vt + i + n, upd(a1, kb1));
+        st4(vt + i + 2 * n, upd(a2, kb2));
+      } else {
+#pragma unroll
+        for (int m = 0; m < XV; ++m) {
+          const float a0 = v[i + m], a1 = v[i + n + m], a2 = v[i + 2 * n + m];
+          vt[i + m] = a0 - eps * (2.f * a0 - kb0[m]);
+          vt[i + n + m] = a1 - eps * (2.f * a1 - kb1[m]);
+          vt[i + 2 * n + m] = a2 - eps * (2.f * a2 - kb2[m]);
+        }
+      }
+    }
+  }
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(3 * kXP(N1 > N2 ? N1 : N2) * (N1 > N2 ? N1 : N2)) void k_fftc_x_fwd(
+    FftPair f) {
+  if (!gate(f.st, f.need_mode)) return;
+  ctx_fwd_body<N1, N2>(f, blockIdx.x);
+}
+
+template <int N1, int N2>
+__global__ __launch_bounds__(3 * kXP(N1 > N2 ? N1 : N2) * (N1 > N2 ? N1 : N2)) void k_fftc_x_inv(
+    FftPair f, UpdArgs u) {
+  if (!gate(u.st, u.need_mode)) return;
+  ctx_inv_body<N1, N2>(f, u, blockIdx.x);
+}
+
+__device__ __forceinline__ bool ctx_fwd_dispatch(const FftPair& f, int block) {
+  switch (f.g.nx) {
+#define LDDMM_CT_CASE(N, A, B)     \
+  case N:                          \
+    ctx_fwd_body<A, B>(f, block);  \
+    return true;
+    LDDMM_CTX_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      return false;
+  }
+}
+
+__device__ __forceinline__ bool ctx_inv_dispatch(const FftPair& f, const UpdArgs& u, int block) {
+  switch (f.g.nx) {
+#define LDDMM_CT_CASE(N, A, B)        \
+  case N:                             \
+    ctx_inv_body<A, B>(f, u, block);  \
+    return true;
+    LDDMM_CTX_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      return false;
+  }
+}
+
 // ----------------------------------------------------------- x forward ----
 // Row rho = z*ny + y.  Rows are processed in pairs (2m, 2m+1): complex lines
 //   Z0 = bx[2m] + i by[2m],  Z1 = bx[2m+1] + i by[2m+1],  Z2 = bz[2m] + i bz[2m+1].
@@ -420,7 +987,10 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd(FftPair f) {
 template <int EMAX>
 __global__ __launch_bounds__(kBlock) void k_fft_x_fwd_batched(BatchRef br) {
   const int p = batch_pair(br, blockIdx.x);
-  x_fwd_body<EMAX>(((const PairTab*)br.tab[p])->fft, blockIdx.x - br.off[p]);
+  const FftPair& f = ((const PairTab*)br.tab[p])->fft;
+  if (!gate(f.st, f.need_mode)) return;
+  if (ctx_fwd_dispatch(f, blockIdx.x - br.off[p])) return;
+  x_fwd_body<EMAX>(f, blockIdx.x - br.off[p]);
 }
 
 // Launch-shape tunables of the FFT passes (results do not depend on them: every
@@ -533,6 +1103,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_y_batched(BatchRef br) {
   const FftPair& f = ((const PairTab*)br.tab[p])->fft;
   const int t = blockIdx.x - br.off[p];
   const int bx = t % f.nbx_y, r = t / f.nbx_y;
+  if (!gate(f.st, f.need_mode)) return;
+  if (ct_y_dispatch<INV>(f, bx, r % f.g.nz, r / f.g.nz)) return;
   y_body<EMAX, INV>(f, bx, r % f.g.nz, r / f.g.nz);
 }
 
@@ -587,6 +1159,8 @@ __global__ __launch_bounds__(kBlock) void k_fft_z_K_batched(BatchRef br) {
   const FftPair& f = ((const PairTab*)br.tab[p])->fft;
   const int t = blockIdx.x - br.off[p];
   const int bx = t % f.nbx_z, r = t / f.nbx_z;
+  if (!gate(f.st, f.need_mode)) return;
+  if (ct_zK_dispatch(f, bx, r % f.g.ny, r / f.g.ny)) return;
   zK_body<EMAX>(f, bx, r % f.g.ny, r / f.g.ny);
 }
 
@@ -698,6 +1272,8 @@ template <int EMAX>
 __global__ __launch_bounds__(kBlock) void k_fft_x_inv_batched(BatchRef br, int j) {
   const int p = batch_pair(br, blockIdx.x);
   const PairTab* t = (const PairTab*)br.tab[p];
+  if (!gate(t->upd[j].st, t->upd[j].need_mode)) return;
+  if (ctx_inv_dispatch(t->fft, t->upd[j], blockIdx.x - br.off[p])) return;
   x_inv_body<EMAX>(t->fft, t->upd[j], blockIdx.x - br.off[p]);
 }
 
@@ -705,9 +1281,15 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv_batched(BatchRef br, int j
 
 // Fill the per-problem tile geometry of the five passes.
 void fft_tiles(FftPair& f, FftLaunch* L) {
-  int ex, ey, ez;
-  f.ppb = pairs_per_block(f.g.nx, &ex);
-  const int ty = tile_cols(f.g.ny, 0, &ey), tz = tile_cols(f.g.nz, 1, &ez);
+  int ex, ey, ez, n1, n2;
+  const bool cx = ctx_plan(f.g.nx, &n1, &n2);
+  f.ppb = cx ? kXP(n1 > n2 ? n1 : n2) : pairs_per_block(f.g.nx, &ex);
+  if (cx) ex = 8;
+  const bool cy = ct_plan(f.g.ny, &n1, &n2), cz = ct_plan(f.g.nz, &n1, &n2);
+  const int ty = cy ? kCT : tile_cols(f.g.ny, 0, &ey);
+  const int tz = cz ? kCT : tile_cols(f.g.nz, 1, &ez);
+  if (cy) ey = 8;
+  if (cz) ez = 8;
   f.lgTXy = ilog2(ty);
   f.lgTXz = ilog2(tz);
   f.nbx_y = (f.g.hx + ty - 1) / ty;
@@ -720,9 +1302,10 @@ void fft_tiles(FftPair& f, FftLaunch* L) {
   L->ez = ez;
   // tile, rounded up to 16 elements, then the axis twiddles (see stage_twiddles)
   auto lds = [](size_t tile, int n) { return ((tile + 15) / 16 * 16 + (size_t)n) * sizeof(float2); };
-  L->x_lds = lds((size_t)3 * f.ppb * f.g.nx, f.g.nx);
-  L->y_lds = lds((size_t)ty * (f.g.ny + 1), f.g.ny);
-  L->z_lds = lds((size_t)tz * (f.g.nz + 1), f.g.nz);
+  L->x_lds = cx ? sizeof(float2) * ((size_t)3 * f.ppb * (f.g.nx + 1) + f.g.nx)
+               : lds((size_t)3 * f.ppb * f.g.nx, f.g.nx);
+  L->y_lds = cy ? ct_lds_bytes(f.g.ny) : lds((size_t)ty * (f.g.ny + 1), f.g.ny);
+  L->z_lds = cz ? ct_lds_bytes(f.g.nz) : lds((size_t)tz * (f.g.nz + 1), f.g.nz);
 }
 
 #define EMAX_SWITCH(E, CALL8, CALL16, CALL32) \
@@ -733,6 +1316,17 @@ void fft_tiles(FftPair& f, FftLaunch* L) {
   } while (0)
 
 void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s) {
+  switch (f.g.nx) {
+#define LDDMM_CT_CASE(N, A, B)                                                              \
+  case N:                                                                                   \
+    hipLaunchKernelGGL((k_fftc_x_fwd<A, B>), dim3(L.x_tiles),                               \
+                       dim3(3 * kXP(A > B ? A : B) * (A > B ? A : B)), L.x_lds, s, f);      \
+    return;
+    LDDMM_CTX_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      break;
+  }
   EMAX_SWITCH(L.ex,
     hipLaunchKernelGGL(k_fft_x_fwd<8>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f),
     hipLaunchKernelGGL(k_fft_x_fwd<16>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f),
@@ -741,6 +1335,19 @@ void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s) {
 
 void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t s) {
   const dim3 grid(f.nbx_y, f.g.nz, 3);
+  switch (f.g.ny) {
+#define LDDMM_CT_CASE(N, A, B)                                                                   \
+  case N:                                                                                        \
+    if (inverse)                                                                                 \
+      hipLaunchKernelGGL((k_fftc_y<A, B, true>), grid, dim3(kCT * (A > B ? A : B)), L.y_lds, s, f); \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_fftc_y<A, B, false>), grid, dim3(kCT * (A > B ? A : B)), L.y_lds, s, f); \
+    return;
+    LDDMM_CT_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      break;
+  }
   if (inverse)
     EMAX_SWITCH(L.ey,
       hipLaunchKernelGGL((k_fft_y<8, true>), grid, dim3(kBlock), L.y_lds, s, f),
@@ -755,6 +1362,16 @@ void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t
 
 void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s) {
   const dim3 grid(f.nbx_z * f.g.ny * 3);
+  switch (f.g.nz) {
+#define LDDMM_CT_CASE(N, A, B)                                                               \
+  case N:                                                                                    \
+    hipLaunchKernelGGL((k_fftc_zK<A, B>), grid, dim3(kCT * (A > B ? A : B)), L.z_lds, s, f); \
+    return;
+    LDDMM_CT_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      break;
+  }
   EMAX_SWITCH(L.ez,
     hipLaunchKernelGGL(k_fft_z_K<8>, grid, dim3(kBlock), L.z_lds, s, f),
     hipLaunchKernelGGL(k_fft_z_K<16>, grid, dim3(kBlock), L.z_lds, s, f),
@@ -762,6 +1379,17 @@ void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s) {
 }
 
 void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hipStream_t s) {
+  switch (f.g.nx) {
+#define LDDMM_CT_CASE(N, A, B)                                                              \
+  case N:                                                                                   \
+    hipLaunchKernelGGL((k_fftc_x_inv<A, B>), dim3(L.x_tiles),                               \
+                       dim3(3 * kXP(A > B ? A : B) * (A > B ? A : B)), L.x_lds, s, f, u);   \
+    return;
+    LDDMM_CTX_PLANS(LDDMM_CT_CASE)
+#undef LDDMM_CT_CASE
+    default:
+      break;
+  }
   EMAX_SWITCH(L.ex,
     hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u),
     hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u),

@@ -24,6 +24,7 @@ by the spacing and upsamples it twice (cell-centred trilinear) to v_init.
 from __future__ import annotations
 
 import json
+import os
 import math
 import time
 
@@ -271,7 +272,7 @@ def first_reaching(D, target):
 
 def _batched_runs(masks, prm, spacing, chunk, device, net=None):
     """Register all pairs in batched launches (from v = 0, or from the network's
-    v_init); returns (traces, wall seconds, seconds spent in the network)."""
+    v_init); returns (masked-SSD traces, wall seconds, seconds spent in the network)."""
     T = prm.T
     m = min(chunk, len(masks))
     wss = [L.workspace((96, 96, 96), prm, spacing, device) for _ in range(m)]
@@ -299,17 +300,36 @@ def _batched_runs(masks, prm, spacing, chunk, device, net=None):
     return traces, time.perf_counter() - t0, t_net
 
 
+def iterations_to_target(D_plain, D_warm):
+    """Per pair: the first iteration at which the plain and the warm-started descent
+    reach the plain method's final masked SSD D* (the last entry of D_plain).  A
+    warm-started run that never reaches it within its iterations is censored at
+    len(trace) (one more than it ran).  Returns (plain, warm, reached) arrays."""
+    kp, kw, hit = [], [], []
+    for dp, dw in zip(D_plain, D_warm):
+        target = dp[-1]
+        kp.append(first_reaching(dp, target))
+        k = first_reaching(dw, target)
+        hit.append(k is not None)
+        kw.append(k if k is not None else len(dw))
+    return np.array(kp), np.array(kw), np.array(hit)
+
+
 def evaluate(net, seeds, spacing=0.05, plain_iters=200, warm_iters=50, chunk=32, device="cuda",
              log=print):
     """Held-out comparison of the plain method (v = 0, plain_iters iterations; its final
-    masked SSD is the target D*) with the network's v_init refined by the same descent.
+    masked SSD is the per-pair target D*) with the network's v_init refined by the same
+    descent, both in batched launches, on every pair.
 
     Wall seconds, inputs in HBM:
-      plain_seq_s     one lddmm_register call per pair (plain_iters each)
-      plain_batched_s the same registrations in batched launches
-      warm_batched_s  network on every pair + batched refinement of warm_iters
-    Iterations to D*: from a warm refinement of plain_iters iterations (its trace), so
-    pairs that need more than warm_iters are counted too."""
+      plain_seq_s         one lddmm_register call per pair (context only)
+      plain_batched_s     the plain registrations in batched launches
+      warm_batched_s      network on every pair + batched refinement of warm_iters
+      warm_batched_long_s network + batched refinement of plain_iters
+    Iterations to D*: the first trace row at or below D*, from the plain_iters runs;
+    a warm-started pair that does not reach D* in plain_iters iterations is censored
+    at plain_iters + 1 and stays in every median (none is dropped).  Time to D* per
+    pair = network time per pair + iterations x the batched time per iteration."""
     from . import synth
     n = len(seeds)
     masks = [synth.warmstart_masks_device(int(s), device) for s in seeds]
@@ -318,37 +338,43 @@ def evaluate(net, seeds, spacing=0.05, plain_iters=200, warm_iters=50, chunk=32,
     ws = L.workspace((96, 96, 96), pp, spacing, device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    D_plain = []
     for M0, M1 in masks:
-        r = L.lddmm_register(M0, M1, params=pp, spacing=spacing, ws=ws, want_phi=False)
-        D_plain.append(r["trace"][:, 2].cpu().numpy())
+        L.lddmm_register(M0, M1, params=pp, spacing=spacing, ws=ws, want_phi=False)
     torch.cuda.synchronize()
     t_plain_seq = time.perf_counter() - t0
-    D_star = np.array([d[-1] for d in D_plain])
     log(f"plain sequential: {n} pairs x {plain_iters} iterations in {t_plain_seq:.2f} s")
-    _, t_plain_batch, _ = _batched_runs(masks, pp, spacing, chunk, device)
+    D_plain, t_plain_batch, _ = _batched_runs(masks, pp, spacing, chunk, device)
     log(f"plain batched: {t_plain_batch:.2f} s")
     D_warm, t_warm_batch, t_net = _batched_runs(masks, pw, spacing, chunk, device, net)
     log(f"warm + batched ({warm_iters} iterations): {t_warm_batch:.2f} s, network {t_net:.2f} s")
     D_warm_long, t_warm_long, t_net_long = _batched_runs(masks, pp, spacing, chunk, device, net)
-    reach = [first_reaching(d, ds) for d, ds in zip(D_warm, D_star)]
-    reach_long = [first_reaching(d, ds) for d, ds in zip(D_warm_long, D_star)]
-    t_iter_warm = (t_warm_long - t_net_long) / (n * plain_iters)      # batched, per pair
-    t_iter_plain = t_plain_seq / (n * plain_iters)                   # sequential, per pair
-    got = [k for k in reach_long if k is not None]
-    t_to_target = [t_net_long / n + k * t_iter_warm for k in got]
+    D_star = np.array([d[-1] for d in D_plain])
+    kp, kw, hit = iterations_to_target(D_plain, D_warm_long)
+    t_iter = t_plain_batch / (n * plain_iters)                  # batched, per pair and iteration
+    t_iter_w = (t_warm_long - t_net_long) / (n * plain_iters)
+    t_plain_to = kp * t_iter
+    t_warm_to = t_net_long / n + kw * t_iter_w
+    t_warm_to_c = np.where(hit, t_warm_to, np.inf)               # censored: never reached
+    saving = kp - kw                                             # censored pairs: <= -1
+    within = [first_reaching(d, ds) for d, ds in zip(D_warm, D_star)]
     return {
         "pairs": n, "plain_iters": plain_iters, "warm_iters": warm_iters,
         "plain_seq_s": t_plain_seq, "plain_batched_s": t_plain_batch,
-        "warm_batched_s": t_warm_batch, "network_s": t_net,
-        "wall_speedup_warm_batched_vs_plain_seq": t_plain_seq / t_warm_batch,
-        "reached_Dstar_within_warm_iters": int(sum(k is not None for k in reach)),
-        "reached_Dstar_within_plain_iters": len(got),
-        "iters_to_Dstar": [k if k is not None else -1 for k in reach_long],
-        "iters_to_Dstar_median": float(np.median(got)) if got else None,
-        "time_to_Dstar_warm_batched_per_pair_s_median": float(np.median(t_to_target))
-        if got else None,
-        "time_to_Dstar_plain_seq_per_pair_s": t_iter_plain * plain_iters,
+        "warm_batched_s": t_warm_batch, "warm_batched_long_s": t_warm_long,
+        "network_s": t_net,
+        "reached_Dstar_within_warm_iters": int(sum(k is not None for k in within)),
+        "reached_Dstar_within_plain_iters": int(hit.sum()),
+        "iters_to_Dstar_plain": kp.tolist(),
+        "iters_to_Dstar_warm": [int(k) if h else -1 for k, h in zip(kw, hit)],
+        "iters_to_Dstar_plain_median": float(np.median(kp)),
+        "iters_to_Dstar_warm_median_censored": float(np.median(np.where(hit, kw, np.inf))),
+        "iters_saving_median_censored": float(np.median(saving)),
+        "iters_saving_mean_reached": float(saving[hit].mean()) if hit.any() else None,
+        "time_to_Dstar_plain_batched_per_pair_s_median": float(np.median(t_plain_to)),
+        "time_to_Dstar_warm_batched_per_pair_s_median_censored": float(np.median(t_warm_to_c)),
+        "time_to_Dstar_plain_batched_total_s": float(t_plain_to.sum()),
+        "time_to_Dstar_warm_batched_total_s_reached_pairs": float(t_warm_to[hit].sum()),
+        "time_to_Dstar_plain_batched_total_s_same_pairs": float(t_plain_to[hit].sum()),
         "D_zero_mean": float(np.mean([d[0] for d in D_plain])),
         "D_plain_at_warm_iters_mean": float(np.mean([d[warm_iters] for d in D_plain])),
         "D_star_mean": float(D_star.mean()),
@@ -369,11 +395,24 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default=None, help="where to save the trained weights")
+    ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
+                    help="skip training: evaluate these saved weights")
     ap.add_argument("--report", default=None)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     L.load()
+    if args.eval_only:
+        net = WarmStartNet.load(args.eval_only)
+        ev = evaluate(net, np.arange(args.eval_seed, args.eval_seed + args.eval_pairs), log=log)
+        report = {"weights": os.path.basename(args.eval_only), "evaluation": ev}
+        log(json.dumps(report))
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(report, f, indent=1)
+        return
+    if not args.out:
+        ap.error("--out is required for training")
     seeds = np.arange(args.first_seed, args.first_seed + args.pairs)
     t0 = time.perf_counter()
     X, Y = make_dataset(seeds, log=log)

@@ -253,15 +253,7 @@ def test_apply_linear_and_nearest_match_oracle():
     outl = L.lddmm_apply(t(u), t(lab, torch.int32), spacing=h,
                          interp=L.INTERP_NEAREST).cpu().numpy()
     # the rounding decision is taken in FP32 on both sides: floor(u*(1/h) + 1/2)
-    d = u * np.float32(1.0 / h) + np.float32(0.5)
-    X = O.index_positions(shape)
-    idx = [np.floor(d[c]).astype(np.int64) + X[c].astype(np.int64) for c in range(3)]
-    ok = np.ones(shape, bool)
-    for c, nn in zip(range(3), (shape[2], shape[1], shape[0])):
-        ok &= (idx[c] >= 0) & (idx[c] < nn)
-    refl = np.where(ok, lab[np.clip(idx[2], 0, shape[0] - 1), np.clip(idx[1], 0, shape[1] - 1),
-                            np.clip(idx[0], 0, shape[2] - 1)], 0)
-    np.testing.assert_array_equal(outl, refl)
+    np.testing.assert_array_equal(outl, O.apply_nearest_f32(u, lab, h))
     # and the FP64 oracle agrees wherever no tie is within FP32 rounding
     ref64 = O.apply_warp(u.astype(np.float64), lab, h, "nearest")
     frac = np.abs((u.astype(np.float64) / h + 0.5) % 1.0)

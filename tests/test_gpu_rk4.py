@@ -103,10 +103,13 @@ def test_rk4_fourth_order_on_the_gpu():
     # trilinear sampling of an affine field is exact, so only the time integration errs:
     # halving the step divides the error by about 2^4 (FP32 keeps it well above rounding)
     say("rk4 order, affine field")
-    e2, e4 = _affine_error(2), _affine_error(4)
-    print("rk4 errors", e2, e4)
+    e2, e4, e8 = _affine_error(2), _affine_error(4), _affine_error(8)
+    print("rk4 errors", e2, e4, e8)
     for k in (0, 1):
         assert e2[k] < 3e-3 and 12.0 < e2[k] / e4[k] < 20.0
+        # at T = 8 the error nears FP32 rounding of 4-voxel displacements, which
+        # bounds the ratio from below less tightly
+        assert np.isfinite(e8[k]) and 6.0 < e4[k] / e8[k] < 20.0
 
 
 def test_rk4_rejected_where_not_defined():

@@ -315,3 +315,34 @@ def test_apply_linear_and_nearest():
     np.testing.assert_array_equal(out, lab)
     out = O.apply_warp(u * 0.6, lab, 1.0, "nearest")
     np.testing.assert_array_equal(out[:, :, :-1], lab[:, :, 1:])
+
+
+def test_nearest_f32_decides_ties_in_float32_and_agrees_away_from_them():
+    # away from ties the FP32 decision equals the FP64 sampler; at an exact
+    # half-integer both round up (floor(y + 1/2)); a displacement whose FP32
+    # product lands on the half-integer rounds as float32 says
+    P = (5, 6, 7)
+    rng = np.random.default_rng(21)
+    lab = rng.integers(1, 50, size=P).astype(np.int32)
+    h = 0.3
+    u = (h * rng.uniform(-2.2, 2.2, size=(3,) + P)).astype(np.float32)
+    f32 = O.apply_nearest_f32(u, lab, h)
+    f64 = O.apply_warp(u.astype(np.float64), lab, h, "nearest")
+    frac = np.abs((u.astype(np.float64) / h + 0.5) % 1.0)
+    safe = np.all((frac > 1e-5) & (frac < 1 - 1e-5), axis=0)
+    assert safe.mean() > 0.99
+    np.testing.assert_array_equal(f32[safe], f64[safe])
+    half = np.zeros((3,) + P, np.float32)
+    half[0] = 0.5                                   # h = 1: exactly half a voxel in x
+    out = O.apply_nearest_f32(half, lab, 1.0)
+    np.testing.assert_array_equal(out[:, :, :-1], lab[:, :, 1:])
+    assert np.all(out[:, :, -1] == 0)
+    # 0.15 / 0.3 in float32 is 0.49999997..., so the FP32 decision keeps the voxel
+    tie = np.zeros((3,) + P, np.float32)
+    tie[1] = np.float32(0.15)
+    d = np.float32(0.15) * np.float32(1.0 / 0.3) + np.float32(0.5)
+    out = O.apply_nearest_f32(tie, lab, 0.3)
+    if np.floor(d) == 0:
+        np.testing.assert_array_equal(out, lab)
+    else:
+        np.testing.assert_array_equal(out[:, :-1], lab[:, 1:])
