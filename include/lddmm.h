@@ -404,6 +404,12 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 #define LDDMM_TUNE_FFT_ZCOLS    3
 #define LDDMM_TUNE_STAGED_MIN_BLOCKS 4
 #define LDDMM_TUNE_FWD_TILES    5
+#define LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS 6   /* the forward sweep reads its map gather
+                                        from an LDS-staged ring of u0 planes (32 x 8
+                                        columns marching z-slabs, as the staged backward)
+                                        on grids that give at least this many blocks
+                                        (at most 4096 blocks); it takes precedence over
+                                        LDDMM_TUNE_FWD_TILES there.  Default 2048. */
 int lddmm_set_tunable(int32_t which, int32_t value);
 
 /* Device copy of n floats, src -> dst (device, not overlapping): the library's

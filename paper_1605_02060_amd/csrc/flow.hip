@@ -168,11 +168,27 @@ __device__ __forceinline__ FwdView<NC> fwd_view(const FwdArgs& a) {
 // Forward step j at voxel i = (x, y, z): the map step, the deformed templates
 // (the residual and the data terms at the last step) and the regulariser term
 // |gamma v - alpha Lap v|^2 from v_j = (vx, vy, vz) and its 7-point Laplacians.
-template <int NC, bool FIRST, bool LAST, bool RK4>
+// The map u0_j at a clamped position, read from global memory: every traversal's
+// sampler gives these bits (the LDS-staged one samples the same 8 corners in the
+// same order).
+template <int NC>
+struct GlobalMapSampler {
+  const FwdView<NC>& f;
+  const Geom& g;
+  __device__ __forceinline__ void operator()(int x, int y, int z, float dx, float dy, float dz,
+                                             float out[3]) const {
+    const Cell cl = make_cell_clamp(g, x, y, z, dx, dy, dz);
+    out[0] = sample(f.U0, cl);
+    out[1] = sample(f.U1, cl);
+    out[2] = sample(f.U2, cl);
+  }
+};
+
+template <int NC, bool FIRST, bool LAST, bool RK4, class MapSampler>
 __device__ __forceinline__ void forward_voxel(const FwdArgs& a, const FwdView<NC>& f, uint32_t i,
                                               int x, int y, int z, float vx, float vy, float vz,
                                               float lapx, float lapy, float lapz, double& accR,
-                                              double& accD, double& accI) {
+                                              double& accD, double& accI, const MapSampler& ms) {
   const Geom& g = a.g;
   const float dt = a.dt, ih = g.inv_h;
   const float c2 = a.alpha * ih * ih;
@@ -180,10 +196,11 @@ __device__ __forceinline__ void forward_voxel(const FwdArgs& a, const FwdView<NC
   if (RK4) rk4_mean(f.V0, f.V1, f.V2, g, x, y, z, -dt * ih, mx, my, mz);
   float ux = -dt * mx, uy = -dt * my, uz = -dt * mz;
   if (!FIRST) {
-    const Cell cl = make_cell_clamp(g, x, y, z, -dt * mx * ih, -dt * my * ih, -dt * mz * ih);
-    ux += sample(f.U0, cl);
-    uy += sample(f.U1, cl);
-    uz += sample(f.U2, cl);
+    float gv[3];
+    ms(x, y, z, -dt * mx * ih, -dt * my * ih, -dt * mz * ih, gv);
+    ux += gv[0];
+    uy += gv[1];
+    uz += gv[2];
   }
   bst(f.W0, i, ux);
   bst(f.W1, i, uy);
@@ -245,7 +262,7 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, ui
     const Nbr nb = periodic_nbr(g, i, x, y, z);
     forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vx, vy, vz, lap7_b(f.V0, nb, vx),
                                         lap7_b(f.V1, nb, vy), lap7_b(f.V2, nb, vz), accR, accD,
-                                        accI);
+                                        accI, GlobalMapSampler<NC>{f, g});
   }
   forward_partials<LAST>(a, tile, accR, accD, accI);
 }
@@ -309,7 +326,8 @@ __device__ __forceinline__ void forward_zmarch_body(const FwdArgs& a, uint32_t t
         lap[c] = lap7_of(bld(V[c], i + dxm), bld(V[c], i + dxp), bld(V[c], i + dym),
                          bld(V[c], i + dyp), vm[c], vp[c], vc[c]);
       forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, (int)z, vc[0], vc[1], vc[2], lap[0],
-                                          lap[1], lap[2], accR, accD, accI);
+                                          lap[1], lap[2], accR, accD, accI,
+                                          GlobalMapSampler<NC>{f, g});
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         vm[c] = vc[c];
@@ -322,9 +340,15 @@ __device__ __forceinline__ void forward_zmarch_body(const FwdArgs& a, uint32_t t
   forward_partials<LAST>(a, tile, accR, accD, accI);
 }
 
-template <int NC, bool FIRST, bool LAST, bool RK4, bool ZM>
+template <int NC, bool FIRST, bool LAST, bool RK4>
+__device__ void forward_staged_body(const FwdArgs& a, int block);
+
+// TRAV: 0 grid-stride, 1 plane-marching, 2 LDS-staged (forward_traversal)
+template <int NC, bool FIRST, bool LAST, bool RK4, int TRAV>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
-  if (ZM)
+  if (TRAV == 2)
+    forward_staged_body<NC, FIRST, LAST, RK4>(a, blockIdx.x);
+  else if (TRAV == 1)
     forward_zmarch_body<NC, FIRST, LAST, RK4>(a, blockIdx.x, gridDim.x);
   else
     forward_body<NC, FIRST, LAST, RK4>(a, blockIdx.x, gridDim.x);
@@ -336,7 +360,9 @@ __global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) 
   const int p = batch_pair(br, blockIdx.x);
   const PairTab* t = (const PairTab*)br.tab[p];
   const uint32_t tile = blockIdx.x - br.off[p], ntiles = br.off[p + 1] - br.off[p];
-  if (t->fwd[j].zmarch)
+  if (t->fwd[j].staged)
+    forward_staged_body<NC, FIRST, LAST, false>(t->fwd[j], (int)tile);
+  else if (t->fwd[j].zmarch)
     forward_zmarch_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
   else
     forward_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
@@ -357,7 +383,10 @@ bool forward_zmarch(const Geom& g) {
   return g_fwd_tiles > 0 && plane_blocks(g) <= kPartMax - (kXCD - 1);
 }
 
+int forward_staged_blocks(const Geom& g);
+
 int forward_tiles(const Geom& g) {
+  if (forward_staged(g)) return forward_staged_blocks(g);
   if (!forward_zmarch(g)) return reduce_grid(g.n);
   const long long nb = plane_blocks(g);
   long long nzc = g_fwd_tiles / nb;                           // runs of planes
@@ -372,16 +401,19 @@ int forward_tiles(const Geom& g) {
 
 template <int NC, bool RK4>
 static void fwd_dispatch(const FwdArgs& a, hipStream_t s) {
-  const int grid = a.zmarch ? forward_tiles(a.g) : reduce_grid(a.g.n);
+  const int grid = (a.staged || a.zmarch) ? forward_tiles(a.g) : reduce_grid(a.g.n);
   const bool first = (a.j == 0), last = (a.j == a.T - 1);
 #define FWD(F, L, Z) \
   hipLaunchKernelGGL((k_forward<NC, F, L, RK4, Z>), dim3(grid), dim3(kBlock), 0, s, a)
-  if (a.zmarch) {
-    if (first && last) FWD(true, true, true); else if (first) FWD(true, false, true);
-    else if (last) FWD(false, true, true); else FWD(false, false, true);
+  if (a.staged) {
+    if (first && last) FWD(true, true, 2); else if (first) FWD(true, false, 2);
+    else if (last) FWD(false, true, 2); else FWD(false, false, 2);
+  } else if (a.zmarch) {
+    if (first && last) FWD(true, true, 1); else if (first) FWD(true, false, 1);
+    else if (last) FWD(false, true, 1); else FWD(false, false, 1);
   } else {
-    if (first && last) FWD(true, true, false); else if (first) FWD(true, false, false);
-    else if (last) FWD(false, true, false); else FWD(false, false, false);
+    if (first && last) FWD(true, true, 0); else if (first) FWD(true, false, 0);
+    else if (last) FWD(false, true, 0); else FWD(false, false, 0);
   }
 #undef FWD
 }
@@ -860,6 +892,128 @@ static void staged_dispatch(const BwdArgs& a, bool hu, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_backward_staged<1, false, RK4>), grid, dim3(kBlock), 0, s, a);
   }
+}
+
+// ------------------------------------------- forward sweep, LDS-staged ----
+// The forward step with the map gather of u0_j read from LDS: a block owns a
+// kBX x kBY column of (x, y) and marches up one z-slab (the tiles and slabs of
+// the staged backward sweep), keeping a ring of u0_j planes z - kBH .. z + kBH
+// (halo kBH, clamped) and loading one new plane per step while the step
+// computes.  A gather whose cell leaves the window reads global memory.  v_j of
+// the planes below, at and above the current one stays in registers (the z
+// terms of the stencil); the in-plane neighbours are loads.  The template gather
+// (displacements of many voxels) stays in global memory.  The per-voxel
+// arithmetic is forward_voxel's with the same 8 corners in the same order, so
+// all traversals give the same bits.
+static int g_fwd_staged_min_blocks = 2048;
+
+void set_fwd_staged_min_blocks(int b) { g_fwd_staged_min_blocks = b < 1 ? 1 : b; }
+
+bool forward_staged(const Geom& g) {
+  const SweepTiling t = sweep_tiling(g);
+  const long long blocks = (long long)t.ntx * t.nty * t.nslab;
+  return blocks >= g_fwd_staged_min_blocks && blocks <= kPartMax && 3LL * g.n < (1LL << 30);
+}
+
+int forward_staged_blocks(const Geom& g) {
+  const SweepTiling t = sweep_tiling(g);
+  return t.ntx * t.nty * t.nslab;
+}
+
+template <int NC>
+struct StagedMapSampler {
+  const MapRing& mu;
+  const FwdView<NC>& f;
+  const Geom& g;
+  int x0, y0;
+  __device__ __forceinline__ void operator()(int x, int y, int z, float dx, float dy, float dz,
+                                             float out[3]) const {
+    int cx, cy, cz;
+    float fx, fy, fz;
+    cell_clamp(x, dx, g.nx, cx, fx);
+    cell_clamp(y, dy, g.ny, cy, fy);
+    cell_clamp(z, dz, g.nz, cz, fz);
+    if (!mu.sample3(x0, y0, z, cx, cy, cz, fx, fy, fz, out))
+      GlobalMapSampler<NC>{f, g}(x, y, z, dx, dy, dz, out);
+  }
+};
+
+template <int NC, bool FIRST, bool LAST, bool RK4>
+__device__ void forward_staged_body(const FwdArgs& a, int block) {
+  __shared__ float su[kBRing][3][kBYH][kBXH];
+  if (a.st->mode == MODE_STOPPED) return;                     // uniform over the grid
+  const Geom g = a.g;
+  const FwdView<NC> f = fwd_view<NC, LAST>(a);
+  const uint32_t n = (uint32_t)g.n;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const uint32_t nxy = (uint32_t)(nx * ny);
+  const SlabTile tt = slab_tile(g, block);
+  const int tx = threadIdx.x % kBX, ty = threadIdx.x / kBX;
+  const int x = tt.x0 + tx, y = tt.y0 + ty;
+  const bool inside = x < nx && y < ny;
+  MapRing mu;
+  mu.s = su;
+  const rsrc_t U = rsrc(a.u_cur, 3u * n);
+  if (!FIRST) {
+    mu.init(g, n, tt.x0, tt.y0);
+    for (int q = tt.zbeg - kBH; q < tt.zbeg + kBH; ++q) {
+      mu.fetch(U, g, q);
+      mu.put(q);
+    }
+    mu.fetch(U, g, tt.zbeg + kBH);
+  }
+  // periodic in-plane neighbours as offsets added to i (modulo 2^32)
+  const uint32_t p = inside ? (uint32_t)(y * nx + x) : 0u;
+  const uint32_t dxm = x == 0 ? (uint32_t)(nx - 1) : 0u - 1u;
+  const uint32_t dxp = x == nx - 1 ? 0u - (uint32_t)(nx - 1) : 1u;
+  const uint32_t dym = y == 0 ? (uint32_t)((ny - 1) * nx) : 0u - (uint32_t)nx;
+  const uint32_t dyp = y == ny - 1 ? 0u - (uint32_t)((ny - 1) * nx) : (uint32_t)nx;
+  const rsrc_t V[3] = {f.V0, f.V1, f.V2};
+  float vm[3] = {0.f, 0.f, 0.f}, vc[3] = {0.f, 0.f, 0.f}, vp[3] = {0.f, 0.f, 0.f};
+  uint32_t zp = tt.zbeg + 1 == nz ? 0u : (uint32_t)tt.zbeg + 1;
+  if (inside) {
+    const uint32_t zb = tt.zbeg == 0 ? (uint32_t)nz - 1 : (uint32_t)tt.zbeg - 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vm[c] = bld(V[c], zb * nxy + p);
+      vc[c] = bld(V[c], (uint32_t)tt.zbeg * nxy + p);
+      vp[c] = bld(V[c], zp * nxy + p);
+    }
+  }
+  const StagedMapSampler<NC> ms{mu, f, g, tt.x0, tt.y0};
+  double accR = 0.0, accD = 0.0, accI = 0.0;
+  for (int z = tt.zbeg; z < tt.zend; ++z) {
+    if (!FIRST) {
+      mu.put(z + kBH);
+      __syncthreads();
+      mu.fetch(U, g, z + kBH + 1);                           // in flight during the step
+    }
+    const uint32_t zn = zp + 1 == (uint32_t)nz ? 0u : zp + 1;  // the plane after next
+    if (inside) {
+      const uint32_t i = (uint32_t)z * nxy + p;
+      float vn[3] = {0.f, 0.f, 0.f};
+      if (z + 1 < tt.zend) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vn[c] = bld(V[c], zn * nxy + p);
+      }
+      float lap[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        lap[c] = lap7_of(bld(V[c], i + dxm), bld(V[c], i + dxp), bld(V[c], i + dym),
+                         bld(V[c], i + dyp), vm[c], vp[c], vc[c]);
+      forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vc[0], vc[1], vc[2], lap[0], lap[1],
+                                          lap[2], accR, accD, accI, ms);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        vm[c] = vc[c];
+        vc[c] = vp[c];
+        vp[c] = vn[c];
+      }
+    }
+    zp = zn;
+    if (!FIRST) __syncthreads();
+  }
+  forward_partials<LAST>(a, (uint32_t)block, accR, accD, accI);
 }
 
 // Batched body-force step: every problem gets backward_partials(g) blocks and

@@ -112,6 +112,7 @@ struct FwdArgs {
   const State* st;
   int rk4;                // departure points by fourth-order Runge-Kutta
   int zmarch;             // plane-marching traversal (forward_tiles blocks), else grid-stride
+  int staged;             // LDS-staged traversal (forward_staged; takes precedence)
 };
 
 struct BwdArgs {
@@ -233,6 +234,8 @@ void launch_forward(const FwdArgs& a, hipStream_t s);
 // single or batched; set_fwd_tiles(0) selects the grid-stride sweep.
 void set_fwd_tiles(int tiles);
 bool forward_zmarch(const Geom& g);
+bool forward_staged(const Geom& g);
+void set_fwd_staged_min_blocks(int blocks);
 int forward_tiles(const Geom& g);
 void launch_backward(const BwdArgs& a, hipStream_t s);
 // Blocks of a body-force launch of the backward sweep on this grid = the min-det

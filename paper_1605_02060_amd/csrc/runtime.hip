@@ -353,6 +353,7 @@ static void forward_steps(Ctx& c, int li, const float* vA, const float* vB, cons
     a.st = c.st;
     a.rk4 = k.rk4;
     a.zmarch = forward_zmarch(L.g);
+    a.staged = forward_staged(L.g);
     ProfScope ps((j == 0 || j == k.T - 1) ? LDDMM_PROF_FORWARD_EDGE : LDDMM_PROF_FORWARD, n, s);
     launch_forward(a, s);
   }
@@ -826,6 +827,7 @@ static void build_pairtab(Ctx& c, int li, PairTab* t) {
     a.partI = c.partI;
     a.st = c.st;
     a.zmarch = forward_zmarch(L.g);
+    a.staged = forward_staged(L.g);
   }
   for (int j = k.T - 1; j >= -1; --j) {
     BwdArgs& a = t->bwd[j + 1];
@@ -1230,6 +1232,11 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
   if (which == LDDMM_TUNE_STAGED_MIN_BLOCKS) {
     if (value < 1) return LDDMM_EINVAL;
     set_staged_min_blocks(value);
+    return LDDMM_OK;
+  }
+  if (which == LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS) {
+    if (value < 1) return LDDMM_EINVAL;
+    set_fwd_staged_min_blocks(value);
     return LDDMM_OK;
   }
   if (which == LDDMM_TUNE_FFT_X_ELEMS) {

@@ -158,6 +158,7 @@ TUNE_FFT_COLS = 2
 TUNE_FFT_ZCOLS = 3
 TUNE_STAGED_MIN_BLOCKS = 4
 TUNE_FWD_TILES = 5
+TUNE_FWD_STAGED_MIN_BLOCKS = 6
 
 PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
                 "other", "hist_range", "hist_count", "hist_apply", "align", "forward_edge",

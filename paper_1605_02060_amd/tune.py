@@ -20,7 +20,8 @@ import torch
 from . import lddmm as L
 
 DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 1024, L.TUNE_FWD_TILES: 3584, L.TUNE_STAGED_MIN_BLOCKS: 2048,
-            L.TUNE_FFT_X_ELEMS: 2048, L.TUNE_FFT_COLS: 16, L.TUNE_FFT_ZCOLS: 8}
+            L.TUNE_FFT_X_ELEMS: 2048, L.TUNE_FFT_COLS: 16, L.TUNE_FFT_ZCOLS: 8,
+            L.TUNE_FWD_STAGED_MIN_BLOCKS: 2048}
 CANDIDATES = {
     L.TUNE_SWEEP_BLOCKS: (512, 1024, 2048, 4096),
     L.TUNE_FWD_TILES: (0, 1792, 2048, 3584, 4096),
@@ -28,11 +29,13 @@ CANDIDATES = {
     L.TUNE_FFT_X_ELEMS: (1024, 2048, 4096),
     L.TUNE_FFT_COLS: (4, 8, 16, 32),
     L.TUNE_FFT_ZCOLS: (4, 8, 16, 32),
+    L.TUNE_FWD_STAGED_MIN_BLOCKS: (1, 1024, 2048, 1 << 30),
 }
 NAMES = {L.TUNE_SWEEP_BLOCKS: "sweep_blocks", L.TUNE_FWD_TILES: "fwd_tiles",
          L.TUNE_STAGED_MIN_BLOCKS: "staged_min_blocks",
          L.TUNE_FFT_X_ELEMS: "fft_x_elems",
-         L.TUNE_FFT_COLS: "fft_cols", L.TUNE_FFT_ZCOLS: "fft_zcols"}
+         L.TUNE_FFT_COLS: "fft_cols", L.TUNE_FFT_ZCOLS: "fft_zcols",
+         L.TUNE_FWD_STAGED_MIN_BLOCKS: "fwd_staged_min_blocks"}
 
 
 def cache_path():

@@ -182,7 +182,7 @@ static void calls_rejected_before_launch() {
 }
 
 static void tunables_strings_profile() {
-  for (int which = 0; which <= 5; ++which) {
+  for (int which = 0; which <= 6; ++which) {
     CHECK(lddmm_set_tunable(which, 0) == (which == LDDMM_TUNE_FWD_TILES ? LDDMM_OK : LDDMM_EINVAL));
     CHECK(lddmm_set_tunable(which, 1 << 30) == LDDMM_OK);
   }
@@ -195,6 +195,7 @@ static void tunables_strings_profile() {
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_ZCOLS, 8) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_STAGED_MIN_BLOCKS, 2048) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FWD_TILES, 3584) == LDDMM_OK);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS, 2048) == LDDMM_OK);
   for (int code = -10; code <= 10; ++code) {
     const char* s = lddmm_strerror(code);
     CHECK(s != nullptr && std::strlen(s) > 0);

@@ -112,7 +112,7 @@ def test_tunable_ids_match_header_and_values_are_checked():
     from paper_1605_02060_amd import tune
     src = open(os.path.join(ROOT, "include", "lddmm.h")).read()
     for name in ("SWEEP_BLOCKS", "FFT_X_ELEMS", "FFT_COLS", "FFT_ZCOLS", "STAGED_MIN_BLOCKS",
-                 "FWD_TILES"):
+                 "FWD_TILES", "FWD_STAGED_MIN_BLOCKS"):
         val = int(re.search(rf"#define LDDMM_TUNE_{name}\s+(\d+)", src).group(1))
         assert getattr(L, f"TUNE_{name}") == val
     assert set(tune.DEFAULTS) == set(tune.CANDIDATES) == set(tune.NAMES)

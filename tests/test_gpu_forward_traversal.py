@@ -125,3 +125,78 @@ def test_tunable_rejects_negative_values(restore_tiles):
     with pytest.raises(Exception):
         L.lddmm_set_tunable(L.TUNE_FWD_TILES, -1)
     L.lddmm_set_tunable(L.TUNE_FWD_TILES, 0)
+
+
+# ----------------------------------------------- LDS-staged forward sweep ----
+# LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS = 1 stages every grid: 32 x 8 columns over
+# z-slabs with a ring of u0 planes in LDS (gathers leaving the window read
+# global memory).  Same expressions, so the same bits as the other traversals.
+
+@pytest.fixture
+def restore_staged():
+    yield
+    L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, 2048)
+    L.lddmm_set_tunable(L.TUNE_FWD_TILES, DEFAULT_TILES)
+
+
+@pytest.mark.parametrize("rk4", [False, True])
+@pytest.mark.parametrize("vmax", [2.0, 40.0])
+def test_staged_forward_gives_the_same_registration(rk4, vmax, restore_staged):
+    # vmax 40 voxels per unit time: 10 voxels per step at T = 4, far outside the window
+    p = synth.blob_pair(SHAPE, 452, max_disp=2.5, sigma=(1.5, 4.0))
+    args = (t(p.M0), t(p.M1), t(p.MI0), t(p.MI1))
+    prm = L.Params(T=4, n_levels=2, iters=(3, 3), step=0.02, guard=False, weight=(1.0, 0.5),
+                   flags=L.FLAG_RK4 if rk4 else 0)
+    P = L.lddmm_comp_grid(SHAPE, prm, 0, 0.05)
+    v0 = t(0.05 * synth.random_velocity(P, 4, 122, vmax=vmax, sigma_s=3.0))
+    out = {}
+    for name, staged, tiles in (("grid", 1 << 30, 0), ("march", 1 << 30, DEFAULT_TILES),
+                                ("staged", 1, DEFAULT_TILES)):
+        say(f"forward traversal {name} rk4={rk4} vmax={vmax}")
+        L.lddmm_set_tunable(L.TUNE_FWD_TILES, tiles)
+        L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, staged)
+        r = L.lddmm_register(*args, params=prm, spacing=0.05, v=v0.clone())
+        torch.cuda.synchronize()
+        out[name] = r
+    ref = out["grid"]
+    for name, r in out.items():
+        assert r["status"] == ref["status"], name
+        for k in ("v", "phi10", "phi01"):
+            assert torch.equal(r[k], ref[k]), (name, k)
+        e, e0 = r["trace"][:, :3], ref["trace"][:, :3]
+        assert torch.allclose(e, e0, rtol=1e-12, atol=0.0), name
+
+
+def test_staged_forward_energy_matches_the_oracle(restore_staged):
+    h, T = 0.05, 4
+    p = synth.blob_pair(SHAPE, 453, max_disp=2.0, sigma=(2.0, 4.0))
+    P = tuple(O.smooth7(n) for n in SHAPE)
+    v = (h * synth.random_velocity(P, T, 123, vmax=6.0, sigma_s=3.0)).astype(np.float32)
+    prm = O.Params(T=T, spacing=h, weight=(1.0, 0.3))
+    ref = O.energy(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm, v.astype(np.float64))
+    lp = L.Params(T=T, n_levels=1, iters=(0,), weight=(1.0, 0.3))
+    L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, 1)
+    say("staged forward: energy vs oracle")
+    out = host(L.lddmm_energy(t(p.M0), t(p.M1), t(p.MI0), t(p.MI1), t(v), lp, spacing=h))
+    for k, name in enumerate(("E", "R", "D", "img_ssd")):
+        assert rel(out[k], ref[name]) < 1e-5, name
+
+
+def test_staged_forward_batched_equals_single(restore_staged):
+    say("batched vs single, staged forward")
+    L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, 1)
+    shapes = [(20, 24, 28), SHAPE, (18, 30, 22)]
+    pairs = []
+    for k, shp in enumerate(shapes):
+        p = synth.blob_pair(shp, 470 + k, max_disp=max(shp) / 10,
+                            sigma=(max(shp) / 16, max(shp) / 6.4))
+        pairs.append({"M0": t(p.M0), "M1": t(p.M1), "spacing": 0.05})
+    prm = L.Params(T=5, n_levels=2, iters=(4, 3), step=0.05, guard=True)
+    res, code = L.lddmm_register_batched(pairs, prm)
+    torch.cuda.synchronize()
+    for d, r in zip(pairs, res):
+        single = L.lddmm_register(d["M0"], d["M1"], params=prm, spacing=d["spacing"])
+        torch.cuda.synchronize()
+        for k in ("v", "phi10", "phi01"):
+            assert torch.equal(r[k], single[k]), k
+        assert torch.equal(r["trace"].nan_to_num(-1.0), single["trace"].nan_to_num(-1.0))
