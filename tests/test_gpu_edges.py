@@ -6,7 +6,8 @@ do not reach:
 * the LDS-staged backward sweep with map gathers that leave its staged window
   (|dt v / h| between 2 and 3 voxels per step), first order and RK4;
 * the exact gradient's splat radius just inside and just beyond its limit;
-* the fold and guard-stop statuses of a registration;
+* the fold and guard-stop statuses of a registration, and a registration
+  resumed from its returned velocity against the straight run;
 * the batched workload's 16 uneven pairs: batched equals single calls, and the
   smallest pair against the oracle.
 Everything is compared with the FP64 oracle on the same seeded inputs, or
@@ -244,6 +245,32 @@ def test_guard_stop_status():
     tr = host(res["trace"])
     assert np.all(tr[1:11, 6] == 0) and np.all(np.isnan(tr[11:, 0]))
     _compare_trace_and_maps(res, ref, 0.05)
+
+
+def test_resume_from_the_returned_velocity_equals_the_straight_run():
+    """Four iterations, then four more from the returned v (v_init), against
+    eight in one call: with every trial accepted the step size never changes, so
+    the resumed call retraces the straight one bit for bit.  The oracle checks
+    the same on its side."""
+    say("resume: 4 + 4 iterations against 8")
+    p = synth.config_pair("blobs32")
+    args = (t(p.M0), t(p.M1), t(p.MI0), t(p.MI1))
+    prm4 = L.Params(T=3, iters=(4,), step=0.02, guard=True)
+    prm8 = L.Params(T=3, iters=(8,), step=0.02, guard=True)
+    a = L.lddmm_register(*args, params=prm4, spacing=0.05)
+    b = L.lddmm_register(*args, params=prm4, spacing=0.05, v=a["v"].clone())
+    c = L.lddmm_register(*args, params=prm8, spacing=0.05)
+    torch.cuda.synchronize()
+    tc = host(c["trace"])
+    assert np.all(tc[1:, 6] == 1)                     # every trial accepted
+    for k in ("v", "phi10", "phi01"):
+        assert torch.equal(b[k], c[k]), k
+    # the resumed trace is the second half of the straight one; its row 0 (the
+    # evaluation at v_init) has the energies of the straight run's row 4
+    tb = host(b["trace"])
+    np.testing.assert_array_equal(tb[1:], tc[5:])
+    np.testing.assert_array_equal(tb[0, [0, 1, 2, 5]], tc[4, [0, 1, 2, 5]])
+    assert b["status"] == c["status"] == L.OK
 
 
 # ------------------------------------------- the 16-pair batched workload ----

@@ -167,6 +167,37 @@ def test_staged_forward_gives_the_same_registration(rk4, vmax, restore_staged):
         assert torch.allclose(e, e0, rtol=1e-12, atol=0.0), name
 
 
+# ragged tiles: x = 45 leaves 13 columns in the last tile and y = 30 six rows;
+# x = 225 = 7 * 32 + 1 leaves one column, whose x - 1 and x + 1 (periodic) both
+# lie outside the tile, and y = 21 five rows
+RAGGED = [(10, 30, 45), (10, 21, 225)]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+@pytest.mark.parametrize("rk4", [False, True])
+def test_staged_forward_on_ragged_tiles(shape, rk4, restore_staged):
+    p = synth.blob_pair(shape, 454, max_disp=2.0, sigma=(1.5, 3.0))
+    args = (t(p.M0), t(p.M1), t(p.MI0), t(p.MI1))
+    prm = L.Params(T=3, n_levels=1, iters=(3,), step=0.02, guard=False, weight=(1.0, 0.5),
+                   flags=L.FLAG_RK4 if rk4 else 0)
+    P = L.lddmm_comp_grid(shape, prm, 0, 0.05)
+    assert P == shape
+    v0 = t(0.05 * synth.random_velocity(P, 3, 124, vmax=3.0, sigma_s=2.0))
+    out = {}
+    for name, staged, tiles in (("grid", 1 << 30, 0), ("staged", 1, DEFAULT_TILES)):
+        say(f"forward traversal {name} on ragged tiles {shape}, rk4={rk4}")
+        L.lddmm_set_tunable(L.TUNE_FWD_TILES, tiles)
+        L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, staged)
+        r = L.lddmm_register(*args, params=prm, spacing=0.05, v=v0.clone())
+        torch.cuda.synchronize()
+        out[name] = r
+    a, b = out["grid"], out["staged"]
+    assert a["status"] == b["status"]
+    for k in ("v", "phi10", "phi01"):
+        assert torch.equal(a[k], b[k]), k
+    assert torch.allclose(a["trace"][:, :3], b["trace"][:, :3], rtol=1e-12, atol=0.0)
+
+
 def test_staged_forward_energy_matches_the_oracle(restore_staged):
     h, T = 0.05, 4
     p = synth.blob_pair(SHAPE, 453, max_disp=2.0, sigma=(2.0, 4.0))
