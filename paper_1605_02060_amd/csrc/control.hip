@@ -67,6 +67,8 @@ __device__ double block1024_min(const double* p, int count, double* red) {
   return block1024_min_of(v, red);
 }
 
+constexpr int kDecideBatch = 16;  // partials in flight per thread in k_decide's pass
+
 // Reduce the energy of the evaluated velocity and take the guard decision.
 //  init = 1 : first evaluation of a level (row 0), no decision.
 //  mode GRAD / RETRY : the slot evaluated a trial in buffer 1 - base.
@@ -94,11 +96,25 @@ __device__ __forceinline__ void decide_body(State* st, const double* partR, int 
     return;
   }
   // one strided pass over the partials of every time step, then one reduction tree
-  // per quantity (the order is fixed, so repeated calls give the same bits)
+  // per quantity (the order is fixed, so repeated calls give the same bits).  The
+  // pass loads kDecideBatch partials before it adds them (in the same order), so
+  // their latencies overlap instead of adding up.
   double R, D, I;
   {
     double r = 0.0, d = 0.0, im = 0.0;
-    for (int i = threadIdx.x; i < T * nfw; i += blockDim.x) {
+    const int n = T * nfw, step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (kDecideBatch - 1) * step < n; i += kDecideBatch * step) {
+      double v[kDecideBatch];
+#pragma unroll
+      for (int u = 0; u < kDecideBatch; ++u) {
+        const int ii = i + u * step, j = ii / nfw;
+        v[u] = partR[(long long)j * kPartMax + (ii - j * nfw)];
+      }
+#pragma unroll
+      for (int u = 0; u < kDecideBatch; ++u) r += v[u];
+    }
+    for (; i < n; i += step) {
       const int j = i / nfw;
       r += partR[(long long)j * kPartMax + (i - j * nfw)];
     }
@@ -114,7 +130,19 @@ __device__ __forceinline__ void decide_body(State* st, const double* partR, int 
   double md = 0.0;
   if (!init && mode == MODE_GRAD) {
     double m = 1e300;
-    for (int i = threadIdx.x; i < T * nbw; i += blockDim.x) {
+    const int n = T * nbw, step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (kDecideBatch - 1) * step < n; i += kDecideBatch * step) {
+      double v[kDecideBatch];
+#pragma unroll
+      for (int u = 0; u < kDecideBatch; ++u) {
+        const int ii = i + u * step, j = ii / nbw;
+        v[u] = partDet[(long long)j * kPartMax + (ii - j * nbw)];
+      }
+#pragma unroll
+      for (int u = 0; u < kDecideBatch; ++u) m = fmin(m, v[u]);
+    }
+    for (; i < n; i += step) {
       const int j = i / nbw;
       m = fmin(m, partDet[(long long)j * kPartMax + (i - j * nbw)]);
     }
@@ -240,9 +268,12 @@ void launch_retry_batched(const BatchRef& br, hipStream_t s) {
   hipLaunchKernelGGL(k_retry_batched, dim3(br.off[br.np]), dim3(kBlock), 0, s, br);
 }
 
+// Most slots accept their trial and the kernel returns at once, so its cost is
+// the dispatch of its blocks: 4096 of them (a grid-stride loop covers the rest)
+// take a few microseconds where one block per 256 elements took about 15.
 void launch_retry(float* vA, float* vB, long long count, const State* st, hipStream_t s) {
   long long b = (count + kBlock - 1) / kBlock;
-  if (b > 65536) b = 65536;
+  if (b > 4096) b = 4096;
   hipLaunchKernelGGL(k_retry, dim3((unsigned)b), dim3(kBlock), 0, s, vA, vB, count, st);
 }
 

@@ -973,8 +973,8 @@ extern "C" int lddmm_register_batched(lddmm_problem* probs, int32_t n, const ldd
       tx[p] = Lf.x_tiles;
       ty[p] = Lf.y_tiles;
       tz[p] = Lf.z_tiles;
-      long long rb = (3 * lv.g.n * k.T + kBlock - 1) / kBlock;
-      tr[p] = (int)(rb > 65536 ? 65536 : rb);
+      long long rb = (3 * lv.g.n * k.T + kBlock - 1) / kBlock;   // as launch_retry
+      tr[p] = (int)(rb > 4096 ? 4096 : rb);
       bp.ex = std::max(bp.ex, Lf.ex);
       bp.ey = std::max(bp.ey, Lf.ey);
       bp.ez = std::max(bp.ez, Lf.ez);
