@@ -396,7 +396,8 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * LDDMM_TUNE_SWEEP_BLOCKS blocks on every grid.  Block counts and traversals
  * change only the order of the FP64 energy partial sums.  A value applies to
  * calls enqueued after it is set.  Returns LDDMM_OK or LDDMM_EINVAL (unknown
- * `which`, or value < 1; value < 0 for LDDMM_TUNE_FWD_TILES).
+ * `which`, or value < 1; value < 0 for LDDMM_TUNE_FWD_TILES and
+ * LDDMM_TUNE_FFT_FUSED_LDS).
  */
 #define LDDMM_TUNE_SWEEP_BLOCKS 0
 #define LDDMM_TUNE_FFT_X_ELEMS  1
@@ -410,6 +411,16 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
                                         on grids that give at least this many blocks
                                         (at most 4096 blocks); it takes precedence over
                                         LDDMM_TUNE_FWD_TILES there.  Default 2048. */
+#define LDDMM_TUNE_FFT_FUSED_LDS 7  /* K transforms x and y in one pass each way,
+                                        with one component's xy plane of the half
+                                        spectrum in LDS, on grids whose (nx, ny) has a
+                                        fused plan ((140, 80), (70, 40), (32, 32),
+                                        (64, 64)) and whose plane needs at most this
+                                        many bytes of LDS; 0 never fuses.  Default
+                                        81920.  The fused passes pack rows of one
+                                        component where the separate passes pack
+                                        rows across components, so K b differs in
+                                        rounding only (FP32). */
 int lddmm_set_tunable(int32_t which, int32_t value);
 
 /* Device copy of n floats, src -> dst (device, not overlapping): the library's

@@ -863,6 +863,319 @@ __device__ __forceinline__ void ctx_inv_body(const FftPair& f, const UpdArgs& u,
   }
 }
 
+// ------------------------------------------ fused x + y passes, LDS plane ----
+// Where the half spectrum of one component's xy plane fits in LDS (hx ny complex
+// values), one block per (component, z plane) transforms x and y in one pass,
+// and y then x with the update on the way back, so the spectrum makes one
+// round trip through HBM per direction less.  Lines pack two rows of the same
+// component, Z_m = b[2m] + i b[2m + 1]; line m occupies the plane rows 2m and
+// 2m + 1 (2 hx >= nx slots) and the Hermitian split turns it into those two
+// half-spectrum rows in place.  The line and column transforms are the
+// two-factor transforms of the other compile-time passes.  Any block size works:
+// lines and columns go round by round.  (The rounding differs from the
+// separate passes, which pack rows across components, within FP32 error.)
+#define LDDMM_FUSED_PLANS(X) \
+  X(140, 14, 10, 80, 10, 8) X(70, 10, 7, 40, 8, 5) X(32, 8, 4, 32, 8, 4) X(64, 8, 8, 64, 8, 8)
+
+constexpr int kFusedBlock = 512;   // threads of a single-problem launch (batched: kBlock)
+constexpr int kFusedBatch = 8;     // global loads in flight per thread in the row loops
+
+// LDS of the fused passes: the plane, then the x and y twiddles.
+static size_t fused_lds_bytes(int nx, int ny) {
+  return sizeof(float2) * ((size_t)ny * (nx / 2 + 1) + nx + ny);
+}
+
+// Two-factor transforms of lines in LDS, in place, natural order in and out:
+// line l at P + l * LSTR, element x at stride ES.  `nl` lines go round by round,
+// blockDim / G per round.
+template <int N1, int N2>
+__device__ __forceinline__ void lds_lines(float2* P, int nl, int lstr, int es, const float2* tw) {
+  constexpr int G = N1 > N2 ? N1 : N2, N = N1 * N2;
+  (void)N;
+  const int per = blockDim.x / G;
+  for (int l0 = 0; l0 < nl; l0 += per) {
+    const int l = l0 + (int)threadIdx.x / G, t = (int)threadIdx.x % G;
+    const bool on = l < nl && (int)threadIdx.x < per * G;
+    float2* line = P + (long long)l * lstr;
+    if (on && t < N1) {
+      float2 v[N2];
+#pragma unroll
+      for (int q = 0; q < N2; ++q) v[q] = line[(t + N1 * q) * es];
+      dft::dft<N2>(v);
+#pragma unroll
+      for (int q = 1; q < N2; ++q) v[q] = dft::mul(v[q], tw[t * q]);
+#pragma unroll
+      for (int q = 0; q < N2; ++q) line[(t + N1 * q) * es] = v[q];
+    }
+    __syncthreads();
+    float2 w[N1];
+    if (on && t < N2) {
+#pragma unroll
+      for (int p = 0; p < N1; ++p) w[p] = line[(p + N1 * t) * es];
+      dft::dft<N1>(w);
+    }
+    __syncthreads();
+    if (on && t < N2) {
+#pragma unroll
+      for (int k = 0; k < N1; ++k) line[(t + N2 * k) * es] = w[k];
+    }
+    __syncthreads();
+  }
+}
+
+// Forward: real b of component c, plane z -> S[c][z][ky][kx].
+template <int NX1, int NX2, int NY1, int NY2>
+__device__ __forceinline__ void fused_fwd_body(const FftPair& f, int c, int z) {
+  constexpr int NX = NX1 * NX2, HX = NX / 2 + 1, NY = NY1 * NY2;
+  constexpr int GY = NY1 > NY2 ? NY1 : NY2;
+  static_assert(NY % 2 == 0 && GY <= 16, "rows pair up; 16 threads per column");
+  extern __shared__ float2 sm[];
+  float2* P = sm;                       // NY rows of HX
+  float2* twx = P + NY * HX;
+  float2* twy = twx + NX;
+  const Geom& g = f.g;
+  for (int e = threadIdx.x; e < NX; e += blockDim.x) twx[e] = f.tw[0][e];
+  for (int e = threadIdx.x; e < NY; e += blockDim.x) twy[e] = f.tw[1][e];
+  // rows of the plane into the lines: row y -> line y / 2, real (even y) or imaginary part
+  // (kFusedBatch loads in flight per thread before their LDS writes)
+  const float* __restrict__ src = f.b + (long long)c * g.n + (long long)z * NY * NX;
+  float* Pf = reinterpret_cast<float*>(P);
+  for (int e0 = 0; e0 < NY * NX; e0 += kFusedBatch * (int)blockDim.x) {
+    float val[kFusedBatch];
+#pragma unroll
+    for (int r = 0; r < kFusedBatch; ++r) {
+      const int e = e0 + r * (int)blockDim.x + (int)threadIdx.x;
+      val[r] = e < NY * NX ? src[e] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kFusedBatch; ++r) {
+      const int e = e0 + r * (int)blockDim.x + (int)threadIdx.x;
+      if (e < NY * NX) {
+        const int y = e / NX, x = e - y * NX;
+        Pf[2 * ((y & ~1) * HX + x) + (y & 1)] = val[r];
+      }
+    }
+  }
+  __syncthreads();
+  lds_lines<NX1, NX2>(P, NY / 2, 2 * HX, 1, twx);
+  // Hermitian split of line m into rows 2m (A) and 2m + 1 (B), through registers,
+  // in rounds of whole lines (all of a line's values are read before any of its
+  // slots is written)
+  const int lr = (4 * (int)blockDim.x) / HX;            // lines per round
+  for (int m0 = 0; m0 < NY / 2; m0 += lr) {
+    const int items = (NY / 2 - m0 < lr ? NY / 2 - m0 : lr) * HX;
+    float2 A[4], B[4];
+    int at[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = r * (int)blockDim.x + (int)threadIdx.x;
+      at[r] = -1;
+      if (e < items) {
+        const int m = m0 + e / HX, k = e % HX;
+        const float2* line = P + 2 * m * HX;
+        const float2 zk = line[k];
+        const float2 zm = dft::conj(line[k == 0 ? 0 : NX - k]);
+        A[r] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+        B[r] = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));
+        at[r] = 2 * m * HX + k;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (at[r] >= 0) {
+        P[at[r]] = A[r];
+        P[at[r] + HX] = B[r];
+      }
+    }
+    __syncthreads();
+  }
+  // columns: blockDim / 16 kx per round, GY <= 16 threads per column
+  const int ncol = (int)blockDim.x / 16;
+  const int cl = (int)threadIdx.x % ncol, t = (int)threadIdx.x / ncol;
+  float2* __restrict__ dst = f.S + (long long)c * g.nspec + (long long)z * NY * g.hs;
+  for (int kx0 = 0; kx0 < HX; kx0 += ncol) {
+    const int kx = kx0 + cl;
+    const bool on = kx < HX && t < GY;
+    if (on && t < NY1) {
+      float2 v[NY2];
+#pragma unroll
+      for (int q = 0; q < NY2; ++q) v[q] = P[(t + NY1 * q) * HX + kx];
+      dft::dft<NY2>(v);
+#pragma unroll
+      for (int q = 1; q < NY2; ++q) v[q] = dft::mul(v[q], twy[t * q]);
+#pragma unroll
+      for (int q = 0; q < NY2; ++q) P[(t + NY1 * q) * HX + kx] = v[q];
+    }
+    __syncthreads();
+    if (on && t < NY2) {
+      float2 w[NY1];
+#pragma unroll
+      for (int p = 0; p < NY1; ++p) w[p] = P[(p + NY1 * t) * HX + kx];
+      dft::dft<NY1>(w);
+#pragma unroll
+      for (int k = 0; k < NY1; ++k) dst[(long long)(t + NY2 * k) * g.hs + kx] = w[k];
+    }
+  }
+}
+
+// Inverse: S[c][z] -> y inverse -> x inverse (Hermitian extension) -> epilogue
+// (the update of v, or g, or Kb) for the rows of component c in plane z.
+template <int NX1, int NX2, int NY1, int NY2>
+__device__ __forceinline__ void fused_inv_body(const FftPair& f, const UpdArgs& u, int c, int z) {
+  constexpr int NX = NX1 * NX2, HX = NX / 2 + 1, NY = NY1 * NY2;
+  constexpr int GY = NY1 > NY2 ? NY1 : NY2;
+  extern __shared__ float2 sm[];
+  float2* P = sm;
+  float2* twx = P + NY * HX;
+  float2* twy = twx + NX;
+  const Geom& g = f.g;
+  const long long n = g.n;
+  for (int e = threadIdx.x; e < NX; e += blockDim.x) twx[e] = f.tw[0][e];
+  for (int e = threadIdx.x; e < NY; e += blockDim.x) twy[e] = f.tw[1][e];
+  __syncthreads();
+  // y inverse of each column, conj(DFT(conj X)), straight from the spectrum
+  const int ncol = (int)blockDim.x / 16;
+  const int cl = (int)threadIdx.x % ncol, t = (int)threadIdx.x / ncol;
+  const float2* __restrict__ src = f.S + (long long)c * g.nspec + (long long)z * NY * g.hs;
+  for (int kx0 = 0; kx0 < HX; kx0 += ncol) {
+    const int kx = kx0 + cl;
+    const bool on = kx < HX && t < GY;
+    if (on && t < NY1) {
+      float2 v[NY2];
+#pragma unroll
+      for (int q = 0; q < NY2; ++q) v[q] = dft::conj(src[(long long)(t + NY1 * q) * g.hs + kx]);
+      dft::dft<NY2>(v);
+#pragma unroll
+      for (int q = 1; q < NY2; ++q) v[q] = dft::mul(v[q], twy[t * q]);
+#pragma unroll
+      for (int q = 0; q < NY2; ++q) P[(t + NY1 * q) * HX + kx] = v[q];
+    }
+    __syncthreads();
+    float2 w[NY1];
+    if (on && t < NY2) {
+#pragma unroll
+      for (int p = 0; p < NY1; ++p) w[p] = P[(p + NY1 * t) * HX + kx];
+      dft::dft<NY1>(w);
+    }
+    __syncthreads();
+    if (on && t < NY2) {
+#pragma unroll
+      for (int k = 0; k < NY1; ++k) P[(t + NY2 * k) * HX + kx] = dft::conj(w[k]);
+    }
+  }
+  __syncthreads();
+  // rows 2m (A) and 2m + 1 (B) -> line m holding conj(Z), Z = A + i B on the
+  // lower half and its Hermitian extension on the upper (through registers, in
+  // rounds of whole lines)
+  const int lr = (4 * (int)blockDim.x) / HX;            // lines per round
+  for (int m0 = 0; m0 < NY / 2; m0 += lr) {
+    const int items = (NY / 2 - m0 < lr ? NY / 2 - m0 : lr) * HX;
+    float2 lo[4], hi[4];
+    int at[4], k_[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = r * (int)blockDim.x + (int)threadIdx.x;
+      at[r] = -1;
+      if (e < items) {
+        const int m = m0 + e / HX, k = e % HX;
+        const float2 A = P[2 * m * HX + k], B = P[(2 * m + 1) * HX + k];
+        lo[r] = make_float2(A.x - B.y, -(A.y + B.x));
+        hi[r] = make_float2(A.x + B.y, A.y - B.x);
+        at[r] = 2 * m * HX;
+        k_[r] = k;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (at[r] >= 0) {
+        const int k = k_[r];
+        if (k < NX) P[at[r] + k] = lo[r];
+        if (k >= 1 && NX - k >= HX) P[at[r] + NX - k] = hi[r];
+      }
+    }
+    __syncthreads();
+  }
+  lds_lines<NX1, NX2>(P, NY / 2, 2 * HX, 1, twx);
+  // result z = conj(DFT(conj Z)): row 2m = Re, row 2m + 1 = Im = -Im of the line
+  const State* st = u.st;
+  float* vA = u.vA;
+  float* vB = u.vB;
+  const int base = st->base;
+  const float eps = (float)st->eps;
+  const long long co = (long long)c * n + (long long)z * NY * NX;   // this plane of component c
+  const long long jo = (long long)u.j * 3 * n;
+  const float* vin = (u.kind == UPD_WRITE_G && u.vfix ? u.vfix : (base ? vB : vA)) + jo + co;
+  float* dst = u.kind == UPD_WRITE_KB ? u.out + co
+               : u.kind == UPD_WRITE_G ? u.out + jo + co : (base ? vA : vB) + jo + co;
+  for (int e0 = 0; e0 < NY * NX; e0 += kFusedBatch * (int)blockDim.x) {
+    float a[kFusedBatch];
+#pragma unroll
+    for (int r = 0; r < kFusedBatch; ++r) {
+      const int e = e0 + r * (int)blockDim.x + (int)threadIdx.x;
+      a[r] = (u.kind != UPD_WRITE_KB && e < NY * NX) ? vin[e] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < kFusedBatch; ++r) {
+      const int e = e0 + r * (int)blockDim.x + (int)threadIdx.x;
+      if (e < NY * NX) {
+        const int y = e / NX, x = e - y * NX;
+        const float2 zz = P[(y & ~1) * HX + x];
+        const float kb = (y & 1) ? -zz.y : zz.x;
+        if (u.kind == UPD_WRITE_KB)
+          dst[e] = kb;
+        else if (u.kind == UPD_WRITE_G)
+          dst[e] = 2.f * a[r] - kb;
+        else
+          dst[e] = a[r] - eps * (2.f * a[r] - kb);
+      }
+    }
+  }
+}
+
+template <int NX1, int NX2, int NY1, int NY2>
+__global__ __launch_bounds__(kFusedBlock) void k_fftf_xy(FftPair f) {
+  if (!gate(f.st, f.need_mode)) return;
+  fused_fwd_body<NX1, NX2, NY1, NY2>(f, (int)blockIdx.x / f.g.nz, (int)blockIdx.x % f.g.nz);
+}
+
+template <int NX1, int NX2, int NY1, int NY2>
+__global__ __launch_bounds__(kFusedBlock) void k_fftf_yx(FftPair f, UpdArgs u) {
+  if (!gate(u.st, u.need_mode)) return;
+  fused_inv_body<NX1, NX2, NY1, NY2>(f, u, (int)blockIdx.x / f.g.nz, (int)blockIdx.x % f.g.nz);
+}
+
+static bool fused_plan(int nx, int ny) {
+#define LDDMM_FUSED_CASE(NX, A, B, NY, C, D) \
+  if (nx == NX && ny == NY) return true;
+  LDDMM_FUSED_PLANS(LDDMM_FUSED_CASE)
+#undef LDDMM_FUSED_CASE
+  return false;
+}
+
+__device__ __forceinline__ bool fused_fwd_dispatch(const FftPair& f, int block) {
+#define LDDMM_FUSED_CASE(NX, A, B, NY, C, D)                                  \
+  if (f.g.nx == NX && f.g.ny == NY) {                                        \
+    fused_fwd_body<A, B, C, D>(f, block / f.g.nz, block % f.g.nz);           \
+    return true;                                                             \
+  }
+  LDDMM_FUSED_PLANS(LDDMM_FUSED_CASE)
+#undef LDDMM_FUSED_CASE
+  return false;
+}
+
+__device__ __forceinline__ bool fused_inv_dispatch(const FftPair& f, const UpdArgs& u, int block) {
+#define LDDMM_FUSED_CASE(NX, A, B, NY, C, D)                                  \
+  if (f.g.nx == NX && f.g.ny == NY) {                                        \
+    fused_inv_body<A, B, C, D>(f, u, block / f.g.nz, block % f.g.nz);        \
+    return true;                                                             \
+  }
+  LDDMM_FUSED_PLANS(LDDMM_FUSED_CASE)
+#undef LDDMM_FUSED_CASE
+  return false;
+}
+
 template <int N1, int N2>
 __global__ __launch_bounds__(3 * kXP(N1 > N2 ? N1 : N2) * (N1 > N2 ? N1 : N2)) void k_fftc_x_fwd(
     FftPair f) {
@@ -989,6 +1302,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_fwd_batched(BatchRef br) {
   const int p = batch_pair(br, blockIdx.x);
   const FftPair& f = ((const PairTab*)br.tab[p])->fft;
   if (!gate(f.st, f.need_mode)) return;
+  if (f.fused && fused_fwd_dispatch(f, blockIdx.x - br.off[p])) return;
   if (ctx_fwd_dispatch(f, blockIdx.x - br.off[p])) return;
   x_fwd_body<EMAX>(f, blockIdx.x - br.off[p]);
 }
@@ -1273,13 +1587,20 @@ __global__ __launch_bounds__(kBlock) void k_fft_x_inv_batched(BatchRef br, int j
   const int p = batch_pair(br, blockIdx.x);
   const PairTab* t = (const PairTab*)br.tab[p];
   if (!gate(t->upd[j].st, t->upd[j].need_mode)) return;
+  if (t->fft.fused && fused_inv_dispatch(t->fft, t->upd[j], blockIdx.x - br.off[p])) return;
   if (ctx_inv_dispatch(t->fft, t->upd[j], blockIdx.x - br.off[p])) return;
   x_inv_body<EMAX>(t->fft, t->upd[j], blockIdx.x - br.off[p]);
 }
 
 // ------------------------------------------------------------- launchers ----
 
-// Fill the per-problem tile geometry of the five passes.
+// Largest LDS of the fused x + y passes (0: never fuse).  Above 80 KB a CU
+// holds one block; the finest atlas level would need 180 KB.
+static int g_fused_lds = 80 * 1024;
+
+void set_fft_fused_lds(int bytes) { g_fused_lds = bytes < 0 ? 0 : bytes; }
+
+// Fill the per-problem tile geometry of the five passes (three when fused).
 void fft_tiles(FftPair& f, FftLaunch* L) {
   int ex, ey, ez, n1, n2;
   const bool cx = ctx_plan(f.g.nx, &n1, &n2);
@@ -1294,8 +1615,10 @@ void fft_tiles(FftPair& f, FftLaunch* L) {
   f.lgTXz = ilog2(tz);
   f.nbx_y = (f.g.hx + ty - 1) / ty;
   f.nbx_z = (f.g.hx + tz - 1) / tz;
-  L->x_tiles = ((f.g.ny * f.g.nz + 1) / 2 + f.ppb - 1) / f.ppb;
-  L->y_tiles = f.nbx_y * f.g.nz * 3;
+  f.fused = g_fused_lds > 0 && fused_plan(f.g.nx, f.g.ny) &&
+            fused_lds_bytes(f.g.nx, f.g.ny) <= (size_t)g_fused_lds;
+  L->x_tiles = f.fused ? 3 * f.g.nz : ((f.g.ny * f.g.nz + 1) / 2 + f.ppb - 1) / f.ppb;
+  L->y_tiles = f.fused ? 0 : f.nbx_y * f.g.nz * 3;
   L->z_tiles = f.nbx_z * f.g.ny * 3;
   L->ex = ex;
   L->ey = ey;
@@ -1304,6 +1627,7 @@ void fft_tiles(FftPair& f, FftLaunch* L) {
   auto lds = [](size_t tile, int n) { return ((tile + 15) / 16 * 16 + (size_t)n) * sizeof(float2); };
   L->x_lds = cx ? sizeof(float2) * ((size_t)3 * f.ppb * (f.g.nx + 1) + f.g.nx)
                : lds((size_t)3 * f.ppb * f.g.nx, f.g.nx);
+  if (f.fused) L->x_lds = fused_lds_bytes(f.g.nx, f.g.ny);
   L->y_lds = cy ? ct_lds_bytes(f.g.ny) : lds((size_t)ty * (f.g.ny + 1), f.g.ny);
   L->z_lds = cz ? ct_lds_bytes(f.g.nz) : lds((size_t)tz * (f.g.nz + 1), f.g.nz);
 }
@@ -1316,6 +1640,16 @@ void fft_tiles(FftPair& f, FftLaunch* L) {
   } while (0)
 
 void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s) {
+  if (f.fused) {
+#define LDDMM_FUSED_CASE(NX, A, B, NY, C, D)                                                   \
+    if (f.g.nx == NX && f.g.ny == NY) {                                                       \
+      hipLaunchKernelGGL((k_fftf_xy<A, B, C, D>), dim3(L.x_tiles), dim3(kFusedBlock), L.x_lds, \
+                         s, f);                                                               \
+      return;                                                                                 \
+    }
+    LDDMM_FUSED_PLANS(LDDMM_FUSED_CASE)
+#undef LDDMM_FUSED_CASE
+  }
   switch (f.g.nx) {
 #define LDDMM_CT_CASE(N, A, B)                                                              \
   case N:                                                                                   \
@@ -1334,6 +1668,7 @@ void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s) {
 }
 
 void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t s) {
+  if (f.fused) return;                    // done by the fused x passes
   const dim3 grid(f.nbx_y, f.g.nz, 3);
   switch (f.g.ny) {
 #define LDDMM_CT_CASE(N, A, B)                                                                   \
@@ -1379,6 +1714,16 @@ void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s) {
 }
 
 void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hipStream_t s) {
+  if (f.fused) {
+#define LDDMM_FUSED_CASE(NX, A, B, NY, C, D)                                                   \
+    if (f.g.nx == NX && f.g.ny == NY) {                                                       \
+      hipLaunchKernelGGL((k_fftf_yx<A, B, C, D>), dim3(L.x_tiles), dim3(kFusedBlock), L.x_lds, \
+                         s, f, u);                                                            \
+      return;                                                                                 \
+    }
+    LDDMM_FUSED_PLANS(LDDMM_FUSED_CASE)
+#undef LDDMM_FUSED_CASE
+  }
   switch (f.g.nx) {
 #define LDDMM_CT_CASE(N, A, B)                                                              \
   case N:                                                                                   \
@@ -1399,6 +1744,7 @@ void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hi
 // Batched passes: every problem of the batch in one launch (register budget and
 // LDS of the most demanding problem).
 void launch_fft_batched(int pass, const BatchRef& br, int emax, size_t lds, int j, hipStream_t s) {
+  if (br.off[br.np] == 0) return;         // every problem's y passes are fused into x
   const dim3 grid(br.off[br.np]);
   switch (pass) {
     case 0:

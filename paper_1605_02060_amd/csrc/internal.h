@@ -168,6 +168,7 @@ struct FftPair {
   int ppb;                 // x passes: row pairs per block
   int lgTXy, nbx_y;        // y pass: log2 tile width, tiles along kx
   int lgTXz, nbx_z;        // z pass
+  int fused;               // x and y in one pass each way (a plane of one component in LDS)
   const State* st;
   int need_mode;
 };
@@ -259,6 +260,7 @@ bool make_plan(int n, FFTPlan* p);
 void launch_twiddles(float2* tw, int n, hipStream_t s);
 void launch_lambda(double* lam, int n, double h, hipStream_t s);
 void fft_tiles(FftPair& f, FftLaunch* L);
+void set_fft_fused_lds(int bytes);
 void launch_fft_x_fwd(const FftPair& f, const FftLaunch& L, hipStream_t s);
 void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t s);
 void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s);

@@ -403,7 +403,7 @@ static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, h
     ProfScope ps(LDDMM_PROF_FFT_X, n, s);
     launch_fft_x_fwd(f, L, s);
   }
-  {
+  if (!f.fused) {
     ProfScope ps(LDDMM_PROF_FFT_Y, n, s);
     launch_fft_y(f, L, 0, s);
   }
@@ -411,7 +411,7 @@ static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, h
     ProfScope ps(LDDMM_PROF_FFT_ZK, n, s);
     launch_fft_z_K(f, L, s);
   }
-  {
+  if (!f.fused) {
     ProfScope ps(LDDMM_PROF_FFT_YINV, n, s);
     launch_fft_y(f, L, 1, s);
   }
@@ -1237,6 +1237,11 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
   if (which == LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS) {
     if (value < 1) return LDDMM_EINVAL;
     set_fwd_staged_min_blocks(value);
+    return LDDMM_OK;
+  }
+  if (which == LDDMM_TUNE_FFT_FUSED_LDS) {
+    if (value < 0) return LDDMM_EINVAL;
+    set_fft_fused_lds(value);
     return LDDMM_OK;
   }
   if (which == LDDMM_TUNE_FFT_X_ELEMS) {

@@ -186,6 +186,9 @@ static void tunables_strings_profile() {
     CHECK(lddmm_set_tunable(which, 0) == (which == LDDMM_TUNE_FWD_TILES ? LDDMM_OK : LDDMM_EINVAL));
     CHECK(lddmm_set_tunable(which, 1 << 30) == LDDMM_OK);
   }
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_FUSED_LDS, -1) == LDDMM_EINVAL);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_FUSED_LDS, 0) == LDDMM_OK);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_FUSED_LDS, 81920) == LDDMM_OK);
   CHECK(lddmm_set_tunable(99, 1) == LDDMM_EINVAL);
   CHECK(lddmm_set_tunable(-1, 1) == LDDMM_EINVAL);
   // back to the defaults
