@@ -3,9 +3,9 @@
 //
 // dft<R>(v): in-place forward DFT of R complex values in natural order,
 //   v[m] <- sum_p v[p] exp(-2 pi i p m / R).
-// Lengths 2, 3, 4, 5, 7, 8 and 16 are written out; 6, 10, 12, 14, 15 and 20
-// are Good-Thomas (prime-factor) products of two coprime lengths, which need
-// no twiddle factors: with N = A B, the input index n = (B a + A b) mod N and
+// Lengths 2, 3, 4, 5, 7, 8, 9 and 16 are written out (9 and 16 as 3 x 3 and
+// 4 x 4 with twiddles); 6, 10, 12, 14, 15 and 20 are Good-Thomas (prime-factor)
+// products of two coprime lengths, which need no twiddle factors: with N = A B, the input index n = (B a + A b) mod N and
 // the output index k (k = ka mod A, k = kb mod B) give
 //   X[k] = sum_a W_A^(a ka) sum_b W_B^(b kb) x[(B a + A b) mod N].
 // Every index is a compile-time constant after unrolling, so the values stay
@@ -58,6 +58,16 @@ struct Roots<7> {
   static constexpr float s[7] = {0.f, 0.78183148246802981f, 0.97492791218182361f,
                                  0.43388373911755812f, -0.43388373911755812f,
                                  -0.97492791218182361f, -0.78183148246802981f};
+};
+template <>
+struct Roots<9> {
+  static constexpr float c[9] = {1.f, 0.76604444311897801f, 0.17364817766693041f, -0.5f,
+                                 -0.93969262078590838f, -0.93969262078590838f, -0.5f,
+                                 0.17364817766693041f, 0.76604444311897801f};
+  static constexpr float s[9] = {0.f, 0.64278760968653925f, 0.98480775301220802f,
+                                 0.86602540378443865f, 0.34202014332566873f,
+                                 -0.34202014332566873f, -0.86602540378443865f,
+                                 -0.98480775301220802f, -0.64278760968653925f};
 };
 template <>
 struct Roots<16> {
@@ -208,6 +218,40 @@ struct DftOdd {
 
 template <>
 struct Dft<3> : DftOdd<3> {};
+
+// 9 = 3 x 3 (Cooley-Tukey): 3-point DFTs over b of x[a + 3 b], twiddles
+// W9^(a kb), 3-point DFTs over a; output X[kb + 3 ka].
+template <>
+struct Dft<9> {
+  static LDDMM_HD void run(float2 (&v)[9]);
+};
+
+LDDMM_HD void Dft<9>::run(float2 (&v)[9]) {
+  float2 y[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float2 t[3] = {v[a], v[a + 3], v[a + 6]};
+    Dft<3>::run(t);
+    y[a][0] = t[0];
+    y[a][1] = t[1];
+    y[a][2] = t[2];
+  }
+#pragma unroll
+  for (int a = 1; a < 3; ++a)
+#pragma unroll
+    for (int kb = 1; kb < 3; ++kb) {
+      const int m = a * kb;
+      y[a][kb] = rot(y[a][kb], Roots<9>::c[m], Roots<9>::s[m]);
+    }
+#pragma unroll
+  for (int kb = 0; kb < 3; ++kb) {
+    float2 t[3] = {y[0][kb], y[1][kb], y[2][kb]};
+    Dft<3>::run(t);
+    v[kb] = t[0];
+    v[kb + 3] = t[1];
+    v[kb + 6] = t[2];
+  }
+}
 template <>
 struct Dft<5> : DftOdd<5> {};
 template <>

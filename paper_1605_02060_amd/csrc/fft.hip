@@ -358,7 +358,10 @@ constexpr int kCT = 16;   // kx columns per tile of a compile-time pass
 
 #define LDDMM_CT_PLANS(X) \
   X(240, 16, 15) X(160, 16, 10) X(120, 12, 10) X(80, 10, 8) X(60, 10, 6) X(40, 8, 5) \
-  X(32, 8, 4) X(64, 8, 8) X(96, 12, 8) X(128, 16, 8) X(70, 10, 7) X(140, 14, 10)
+  X(32, 8, 4) X(64, 8, 8) X(96, 12, 8) X(128, 16, 8) X(70, 10, 7) X(140, 14, 10) \
+  X(72, 12, 6) X(75, 15, 5) X(81, 9, 9) X(84, 12, 7) X(90, 15, 6) X(98, 14, 7) \
+  X(100, 10, 10) X(105, 15, 7) X(108, 12, 9) X(112, 16, 7) X(126, 14, 9) X(135, 15, 9) \
+  X(144, 12, 12) X(150, 15, 10)
 
 static bool ct_plan(int n, int* n1, int* n2) {
 #define LDDMM_CT_CASE(N, A, B) \

@@ -67,6 +67,24 @@ def test_smooth_matches_oracle(P, h, alpha, gamma):
     assert err < 1e-5, err
 
 
+# every length with a compile-time plan added for the batched workload's grids,
+# along x (the packed real passes) and along y and z (the complex passes)
+NEW_PLANS = [72, 75, 81, 84, 90, 98, 100, 105, 108, 112, 126, 135, 144, 150]
+
+
+@pytest.mark.parametrize("k", range(len(NEW_PLANS)))
+def test_smooth_compile_time_plans_match_oracle(k):
+    n = len(NEW_PLANS)
+    P = (NEW_PLANS[(k + 9) % n], NEW_PLANS[(k + 5) % n], NEW_PLANS[k])   # [z][y][x]
+    say(f"smooth on compile-time plans P={P}")
+    b = np.random.default_rng(20 + k).normal(size=(3,) + P)
+    out = L.lddmm_smooth(t(b), 0.1, 0.02, 1.0)
+    torch.cuda.synchronize()
+    ref = O.apply_K(b, 0.02, 1.0, 0.1)
+    err = np.abs(host(out) - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
+
+
 # ---------------------------------------------------------- energy ----
 
 CASES = [
