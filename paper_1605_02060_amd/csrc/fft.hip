@@ -893,8 +893,7 @@ static size_t fused_lds_bytes(int nx, int ny) {
 // blockDim / G per round.
 template <int N1, int N2>
 __device__ __forceinline__ void lds_lines(float2* P, int nl, int lstr, int es, const float2* tw) {
-  constexpr int G = N1 > N2 ? N1 : N2, N = N1 * N2;
-  (void)N;
+  constexpr int G = N1 > N2 ? N1 : N2;
   const int per = blockDim.x / G;
   for (int l0 = 0; l0 < nl; l0 += per) {
     const int l = l0 + (int)threadIdx.x / G, t = (int)threadIdx.x % G;
