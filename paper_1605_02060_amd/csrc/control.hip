@@ -27,36 +27,40 @@ void launch_level_begin(State* st, double step, int keep_flags, hipStream_t s) {
 }
 
 // Three sums over one 1024-thread block at once (per-thread values in, totals out
-// in every thread); red holds 3 x 1024 doubles.
+// in every thread): a fixed shuffle tree within each wavefront, then the 16
+// wavefront sums in order; red holds at least 3 x 16 doubles.
 __device__ void block1024_sum3(double& a, double& b, double& c, double* red) {
-  const int t = threadIdx.x, n = blockDim.x;
-  red[t] = a;
-  red[n + t] = b;
-  red[2 * n + t] = c;
-  __syncthreads();
-  for (int s = n / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      red[t] += red[t + s];
-      red[n + t] += red[n + t + s];
-      red[2 * n + t] += red[2 * n + t + s];
-    }
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+    c += __shfl_down(c, off, 64);
   }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    red[wid] = a;
+    red[16 + wid] = b;
+    red[32 + wid] = c;
+  }
+  __syncthreads();
   a = red[0];
-  b = red[n];
-  c = red[2 * n];
+  b = red[16];
+  c = red[32];
+  for (int w = 1; w < nw; ++w) {
+    a += red[w];
+    b += red[16 + w];
+    c += red[32 + w];
+  }
   __syncthreads();
 }
 
-// Minimum of one value per thread over a 1024-thread block.
+// Minimum of one value per thread over a 1024-thread block (every thread gets it).
 __device__ double block1024_min_of(double v, double* red) {
-  red[threadIdx.x] = v;
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) red[wid] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int w = 1; w < nw; ++w) r = fmin(r, red[w]);
   __syncthreads();
   return r;
 }
