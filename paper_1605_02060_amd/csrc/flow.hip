@@ -530,9 +530,11 @@ __global__ __launch_bounds__(kBlock) void k_backward_batched(BatchRef br, int sl
 //  - the deformed template: planes z - 1 .. z + 1, halo 1 (its gradient).
 // The residual gather (displacements of many voxels) stays in global memory.
 // The arithmetic and its order are those of backward_body, so both give the
-// same bits.  (The same staging of the forward step measured no faster: its
-// cost is in the template gather, which cannot be staged.)
-constexpr int kBX = 32, kBY = 8, kBH = 2;
+// same bits.  The halo is 1: the stencil needs no more, and a map gather of
+// less than a voxel per step (the usual case: about 0.3 voxel in the atlas
+// workload) stays in the window; filling a halo-2 ring cost more than the
+// gathers between one and two voxels it kept in LDS.
+constexpr int kBX = 32, kBY = 8, kBH = 1;
 constexpr int kBRing = 2 * kBH + 1;
 constexpr int kBXH = kBX + 2 * kBH, kBYH = kBY + 2 * kBH;     // map window
 constexpr int kBXJ = kBX + 2, kBYJ = kBY + 2;                 // halo-1 window
