@@ -125,7 +125,7 @@ def test_sigma_half_register():
 @pytest.mark.parametrize("integrator", ["euler", "rk4"])
 def test_staged_backward_with_gathers_outside_the_window(integrator):
     """max |dt v / h| of 2.5 voxels: most map gathers of the staged kernel leave
-    its LDS window (halo 2) and read global memory."""
+    its LDS window (halo 1) and read global memory."""
     say(f"staged backward, 2.5 voxels per step, {integrator}")
     shape, T, h = (40, 36, 48), 4, 0.1
     p = synth.blob_pair(shape, 33, max_disp=4.0, sigma=(3.0, 7.0))
