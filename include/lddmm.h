@@ -386,7 +386,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * kx columns per tile of the y / the z pass (rounded down to a power of two in
  * [2, 32], then halved while columns x length exceeds 4096; defaults 16 and 8).
  * LDDMM_TUNE_STAGED_MIN_BLOCKS: the backward sweep uses its LDS-staged kernel
- * on grids that give at least this many blocks (one per 32 x 8 column and
+ * on grids that give at least this many blocks (one per 64 x 4 column and
  * z-slab; default 2048, at most 4096 blocks).  LDDMM_TUNE_FWD_TILES: the
  * forward sweep gives each thread a column of one xy plane block (256 voxels)
  * and a run of consecutive z-planes, with at most this many blocks where that
@@ -406,7 +406,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
 #define LDDMM_TUNE_STAGED_MIN_BLOCKS 4
 #define LDDMM_TUNE_FWD_TILES    5
 #define LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS 6   /* the forward sweep reads its map gather
-                                        from an LDS-staged ring of u0 planes (32 x 8
+                                        from an LDS-staged ring of u0 planes (64 x 4
                                         columns marching z-slabs, as the staged backward)
                                         on grids that give at least this many blocks
                                         (at most 4096 blocks); it takes precedence over

@@ -533,8 +533,11 @@ __global__ __launch_bounds__(kBlock) void k_backward_batched(BatchRef br, int sl
 // same bits.  The halo is 1: the stencil needs no more, and a map gather of
 // less than a voxel per step (the usual case: about 0.3 voxel in the atlas
 // workload) stays in the window; filling a halo-2 ring cost more than the
-// gathers between one and two voxels it kept in LDS.
-constexpr int kBX = 32, kBY = 8, kBH = 1;
+// gathers between one and two voxels it kept in LDS.  The columns are 64 x 4:
+// a wavefront then owns one 64-voxel row segment, whose loads touch fewer cache
+// lines than the two 32-voxel segments of a 32 x 8 column, which pays for the
+// taller halo (66 x 6 against 34 x 10 staged values per 256 voxels).
+constexpr int kBX = 64, kBY = 4, kBH = 1;
 constexpr int kBRing = 2 * kBH + 1;
 constexpr int kBXH = kBX + 2 * kBH, kBYH = kBY + 2 * kBH;     // map window
 constexpr int kBXJ = kBX + 2, kBYJ = kBY + 2;                 // halo-1 window
@@ -795,8 +798,10 @@ __device__ __forceinline__ void backward_staged_body(const BwdArgs& a, int block
     mu.put(z + kBH);
     rj.put(z + 1);
     __syncthreads();
-    mu.fetch(UN, g, z + kBH + 1);                            // in flight during the step
-    rj.fetch(JJ, g, z + 2);
+    if (z + 1 < tt.zend) {                                   // in flight during the step
+      mu.fetch(UN, g, z + kBH + 1);
+      rj.fetch(JJ, g, z + 2);
+    }
     if (inside) {
       const uint32_t i = (uint32_t)((z * ny + y) * nx + x);
       const int s0 = z % kBRing;
@@ -991,7 +996,7 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
     if (!FIRST) {
       mu.put(z + kBH);
       __syncthreads();
-      mu.fetch(U, g, z + kBH + 1);                           // in flight during the step
+      if (z + 1 < tt.zend) mu.fetch(U, g, z + kBH + 1);      // in flight during the step
     }
     const uint32_t zn = zp + 1 == (uint32_t)nz ? 0u : zp + 1;  // the plane after next
     if (inside) {

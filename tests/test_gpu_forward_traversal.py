@@ -128,7 +128,7 @@ def test_tunable_rejects_negative_values(restore_tiles):
 
 
 # ----------------------------------------------- LDS-staged forward sweep ----
-# LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS = 1 stages every grid: 32 x 8 columns over
+# LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS = 1 stages every grid: 64 x 4 columns over
 # z-slabs with a ring of u0 planes in LDS (gathers leaving the window read
 # global memory).  Same expressions, so the same bits as the other traversals.
 
@@ -167,10 +167,12 @@ def test_staged_forward_gives_the_same_registration(rk4, vmax, restore_staged):
         assert torch.allclose(e, e0, rtol=1e-12, atol=0.0), name
 
 
-# ragged tiles: x = 45 leaves 13 columns in the last tile and y = 30 six rows;
-# x = 225 = 7 * 32 + 1 leaves one column, whose x - 1 and x + 1 (periodic) both
-# lie outside the tile, and y = 21 five rows
-RAGGED = [(10, 30, 45), (10, 21, 225)]
+# ragged tiles (64 x 4 columns): x = 45 fills 45 columns of one tile and y = 30
+# leaves two rows in the last tile; x = 225 = 3 * 64 + 33 and y = 21 one row;
+# x = 450 = 7 * 64 + 2 leaves two columns, the last of whose x + 1 (periodic)
+# lies in the first tile, and y = 9 one row.  (A one-column tile would need a
+# 7-smooth x of 64 k + 1; the first is 2625, above the largest axis, 1024.)
+RAGGED = [(10, 30, 45), (10, 21, 225), (10, 9, 450)]
 
 
 @pytest.mark.parametrize("shape", RAGGED)
