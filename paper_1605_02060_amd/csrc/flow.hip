@@ -184,11 +184,25 @@ struct GlobalMapSampler {
   }
 };
 
-template <int NC, bool FIRST, bool LAST, bool RK4, class MapSampler>
+// The weighted template channels with zero outside the grid at (x, y, z) + d.
+template <int NC>
+struct GlobalTemplateSampler {
+  const FwdView<NC>& f;
+  const Geom& g;
+  __device__ __forceinline__ void operator()(int x, int y, int z, float dx, float dy, float dz,
+                                             float out[NC]) const {
+    const Cell cz = make_cell_zero(g, x, y, z, dx, dy, dz);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = sample(f.T0[c], cz);
+  }
+};
+
+template <int NC, bool FIRST, bool LAST, bool RK4, class MapSampler, class TemplateSampler>
 __device__ __forceinline__ void forward_voxel(const FwdArgs& a, const FwdView<NC>& f, uint32_t i,
                                               int x, int y, int z, float vx, float vy, float vz,
                                               float lapx, float lapy, float lapz, double& accR,
-                                              double& accD, double& accI, const MapSampler& ms) {
+                                              double& accD, double& accI, const MapSampler& ms,
+                                              const TemplateSampler& ts) {
   const Geom& g = a.g;
   const float dt = a.dt, ih = g.inv_h;
   const float c2 = a.alpha * ih * ih;
@@ -207,10 +221,11 @@ __device__ __forceinline__ void forward_voxel(const FwdArgs& a, const FwdView<NC
   bst(f.W2, i, uz);
   // deformed templates at t_{j+1}
   {
-    const Cell cz = make_cell_zero(g, x, y, z, ux * ih, uy * ih, uz * ih);
+    float tv[NC];
+    ts(x, y, z, ux * ih, uy * ih, uz * ih, tv);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const float val = sample(f.T0[c], cz);
+      const float val = tv[c];
       if (!LAST) {
         bst(f.OUT[c], i, val);
       } else {
@@ -221,6 +236,7 @@ __device__ __forceinline__ void forward_voxel(const FwdArgs& a, const FwdView<NC
       }
     }
     if (LAST && a.img_ch >= 0 && !a.img_weighted) {
+      const Cell cz = make_cell_zero(g, x, y, z, ux * ih, uy * ih, uz * ih);
       const float d = sample(f.IM0, cz) - bld(f.IM1, i);
       accI += (double)d * (double)d;
     }
@@ -262,7 +278,8 @@ __device__ __forceinline__ void forward_body(const FwdArgs& a, uint32_t tile, ui
     const Nbr nb = periodic_nbr(g, i, x, y, z);
     forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vx, vy, vz, lap7_b(f.V0, nb, vx),
                                         lap7_b(f.V1, nb, vy), lap7_b(f.V2, nb, vz), accR, accD,
-                                        accI, GlobalMapSampler<NC>{f, g});
+                                        accI, GlobalMapSampler<NC>{f, g},
+                                        GlobalTemplateSampler<NC>{f, g});
   }
   forward_partials<LAST>(a, tile, accR, accD, accI);
 }
@@ -327,7 +344,8 @@ __device__ __forceinline__ void forward_zmarch_body(const FwdArgs& a, uint32_t t
                          bld(V[c], i + dyp), vm[c], vp[c], vc[c]);
       forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, (int)z, vc[0], vc[1], vc[2], lap[0],
                                           lap[1], lap[2], accR, accD, accI,
-                                          GlobalMapSampler<NC>{f, g});
+                                          GlobalMapSampler<NC>{f, g},
+                                          GlobalTemplateSampler<NC>{f, g});
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         vm[c] = vc[c];
@@ -691,6 +709,19 @@ struct HaloRing {
       }
     }
   }
+  // One component: the window is that of a map ring with halo 1, whose element e
+  // of component 0 has the same in-plane offset, so its offsets are taken over.
+  __device__ __forceinline__ void init_from(const MapRing& m) {
+    static_assert(K == 1 && kBH == 1 && kBXJ == kBXH && kBYJ == kBYH && kRegs <= kURegs,
+                  "the same window");
+    ok = 0u;
+    c1 = 0u;
+#pragma unroll
+    for (int r = 0; r < kRegs; ++r) {
+      off[r] = m.off[r];
+      if (threadIdx.x + r * kBlock < kPlane) ok |= m.ok & (1u << r);
+    }
+  }
   // Plane p of every component into registers; component c is read through R[c].
   __device__ __forceinline__ void fetch(const rsrc_t* R, const Geom& g, int p) {
     const bool pin = p >= 0 && p < g.nz;
@@ -702,14 +733,30 @@ struct HaloRing {
       reg[r] = val;
     }
   }
+  // Plane p >= -1 into slot (p + 3) mod 3 (the planes outside the grid as zeros).
   __device__ __forceinline__ void put(int p) {
-    if (p < 0) return;
-    float* base = &s[p % 3][0][0][0];
+    float* base = &s[(p + 3) % 3][0][0][0];
 #pragma unroll
     for (int r = 0; r < kRegs; ++r) {
       const int e = threadIdx.x + r * kBlock;
       if (e < kPlane) base[e] = reg[r];
     }
+  }
+  // Whether the 8 corners of cell (cx, cy, cz) lie in the window of step z:
+  // columns x0 - 1 .. x0 + kBX, rows y0 - 1 .. y0 + kBY, planes z - 1 .. z + 1.
+  __device__ __forceinline__ static bool covers(int x0, int y0, int z, int cx, int cy, int cz) {
+    const int wx = cx - (x0 - 1), wy = cy - (y0 - 1);
+    return wx >= 0 && wx + 1 < kBXJ && wy >= 0 && wy + 1 < kBYJ && cz >= z - 1 && cz <= z;
+  }
+  // Trilinear sample of component c at a covered cell, zero outside the grid (the
+  // staged planes hold zeros there), corners in the order of sample().
+  __device__ __forceinline__ float lerp(int c, int x0, int y0, int cx, int cy, int cz, float fx,
+                                        float fy, float fz) const {
+    const int wx = cx - (x0 - 1), wy = cy - (y0 - 1);
+    const int za = (cz + 3) % 3, zb = (cz + 4) % 3;
+    return lerp8(s[za][c][wy][wx], s[za][c][wy][wx + 1], s[za][c][wy + 1][wx],
+                 s[za][c][wy + 1][wx + 1], s[zb][c][wy][wx], s[zb][c][wy][wx + 1],
+                 s[zb][c][wy + 1][wx], s[zb][c][wy + 1][wx + 1], fx, fy, fz);
   }
 };
 
@@ -948,9 +995,40 @@ struct StagedMapSampler {
   }
 };
 
+// The template channels at (x, y, z) + d from the staged template planes
+// z - 1 .. z + 1 when the cell lies in the window, else from global memory; the
+// same cell, fractions and corner order either way.
+template <int NC>
+struct StagedTemplateSampler {
+  const HaloRing<NC>& rt;
+  const FwdView<NC>& f;
+  const Geom& g;
+  int x0, y0;
+  __device__ __forceinline__ void operator()(int x, int y, int z, float dx, float dy, float dz,
+                                             float out[NC]) const {
+    int cx, cy, cz;
+    float fx, fy, fz;
+    cell_free(x, dx, g.nx, cx, fx);
+    cell_free(y, dy, g.ny, cy, fy);
+    cell_free(z, dz, g.nz, cz, fz);
+    if (HaloRing<NC>::covers(x0, y0, z, cx, cy, cz)) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) out[c] = rt.lerp(c, x0, y0, cx, cy, cz, fx, fy, fz);
+    } else {
+      GlobalTemplateSampler<NC>{f, g}(x, y, z, dx, dy, dz, out);
+    }
+  }
+};
+
 template <int NC, bool FIRST, bool LAST, bool RK4>
 __device__ void forward_staged_body(const FwdArgs& a, int block) {
+  // The template channel is staged too in the first-order steps that are not the
+  // last, with one weighted channel (the last step, the RK4 steps and a second
+  // channel hold more live registers, and the ring would cost a wave per SIMD).
+  constexpr bool TR = NC == 1 && !LAST && !RK4;
+  constexpr bool SYNC = !FIRST || TR;                         // a ring to fill
   __shared__ float su[kBRing][3][kBYH][kBXH];
+  __shared__ float stp[TR ? 3 : 1][NC][kBYJ][kBXJ];
   if (a.st->mode == MODE_STOPPED) return;                     // uniform over the grid
   const Geom g = a.g;
   const FwdView<NC> f = fwd_view<NC, LAST>(a);
@@ -971,6 +1049,19 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
       mu.put(q);
     }
     mu.fetch(U, g, tt.zbeg + kBH);
+  }
+  HaloRing<NC> rt;                                            // template planes z - 1 .. z + 1
+  if constexpr (TR) {
+    rt.s = stp;
+    if constexpr (!FIRST)
+      rt.init_from(mu);
+    else
+      rt.init(g, tt.x0, tt.y0);
+    for (int q = tt.zbeg - 1; q <= tt.zbeg; ++q) {
+      rt.fetch(f.T0, g, q);
+      rt.put(q);
+    }
+    rt.fetch(f.T0, g, tt.zbeg + 1);
   }
   // periodic in-plane neighbours as offsets added to i (modulo 2^32)
   const uint32_t p = inside ? (uint32_t)(y * nx + x) : 0u;
@@ -993,10 +1084,12 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
   const StagedMapSampler<NC> ms{mu, f, g, tt.x0, tt.y0};
   double accR = 0.0, accD = 0.0, accI = 0.0;
   for (int z = tt.zbeg; z < tt.zend; ++z) {
-    if (!FIRST) {
-      mu.put(z + kBH);
-      __syncthreads();
-      if (z + 1 < tt.zend) mu.fetch(U, g, z + kBH + 1);      // in flight during the step
+    if (!FIRST) mu.put(z + kBH);
+    if (TR) rt.put(z + 1);
+    if (SYNC) __syncthreads();
+    if (z + 1 < tt.zend) {                                    // in flight during the step
+      if (!FIRST) mu.fetch(U, g, z + kBH + 1);
+      if (TR) rt.fetch(f.T0, g, z + 2);
     }
     const uint32_t zn = zp + 1 == (uint32_t)nz ? 0u : zp + 1;  // the plane after next
     if (inside) {
@@ -1011,8 +1104,14 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
       for (int c = 0; c < 3; ++c)
         lap[c] = lap7_of(bld(V[c], i + dxm), bld(V[c], i + dxp), bld(V[c], i + dym),
                          bld(V[c], i + dyp), vm[c], vp[c], vc[c]);
-      forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vc[0], vc[1], vc[2], lap[0], lap[1],
-                                          lap[2], accR, accD, accI, ms);
+      if constexpr (TR)
+        forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vc[0], vc[1], vc[2], lap[0], lap[1],
+                                            lap[2], accR, accD, accI, ms,
+                                            StagedTemplateSampler<NC>{rt, f, g, tt.x0, tt.y0});
+      else
+        forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vc[0], vc[1], vc[2], lap[0], lap[1],
+                                            lap[2], accR, accD, accI, ms,
+                                            GlobalTemplateSampler<NC>{f, g});
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         vm[c] = vc[c];
@@ -1021,7 +1120,7 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
       }
     }
     zp = zn;
-    if (!FIRST) __syncthreads();
+    if (SYNC) __syncthreads();
   }
   forward_partials<LAST>(a, (uint32_t)block, accR, accD, accI);
 }

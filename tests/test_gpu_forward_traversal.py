@@ -139,20 +139,23 @@ def restore_staged():
     L.lddmm_set_tunable(L.TUNE_FWD_TILES, DEFAULT_TILES)
 
 
+# weight (1, 0) leaves one weighted channel, whose template planes the first-order
+# interior steps also stage in LDS; (1, 0.5) weights two, read from global memory
+@pytest.mark.parametrize("weight", [(1.0, 0.5), (1.0, 0.0)])
 @pytest.mark.parametrize("rk4", [False, True])
 @pytest.mark.parametrize("vmax", [2.0, 40.0])
-def test_staged_forward_gives_the_same_registration(rk4, vmax, restore_staged):
+def test_staged_forward_gives_the_same_registration(rk4, vmax, weight, restore_staged):
     # vmax 40 voxels per unit time: 10 voxels per step at T = 4, far outside the window
     p = synth.blob_pair(SHAPE, 452, max_disp=2.5, sigma=(1.5, 4.0))
     args = (t(p.M0), t(p.M1), t(p.MI0), t(p.MI1))
-    prm = L.Params(T=4, n_levels=2, iters=(3, 3), step=0.02, guard=False, weight=(1.0, 0.5),
+    prm = L.Params(T=4, n_levels=2, iters=(3, 3), step=0.02, guard=False, weight=weight,
                    flags=L.FLAG_RK4 if rk4 else 0)
     P = L.lddmm_comp_grid(SHAPE, prm, 0, 0.05)
     v0 = t(0.05 * synth.random_velocity(P, 4, 122, vmax=vmax, sigma_s=3.0))
     out = {}
     for name, staged, tiles in (("grid", 1 << 30, 0), ("march", 1 << 30, DEFAULT_TILES),
                                 ("staged", 1, DEFAULT_TILES)):
-        say(f"forward traversal {name} rk4={rk4} vmax={vmax}")
+        say(f"forward traversal {name} rk4={rk4} vmax={vmax} weight={weight}")
         L.lddmm_set_tunable(L.TUNE_FWD_TILES, tiles)
         L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, staged)
         r = L.lddmm_register(*args, params=prm, spacing=0.05, v=v0.clone())
@@ -175,19 +178,20 @@ def test_staged_forward_gives_the_same_registration(rk4, vmax, restore_staged):
 RAGGED = [(10, 30, 45), (10, 21, 225), (10, 9, 450)]
 
 
+@pytest.mark.parametrize("weight", [(1.0, 0.5), (1.0, 0.0)])
 @pytest.mark.parametrize("shape", RAGGED)
 @pytest.mark.parametrize("rk4", [False, True])
-def test_staged_forward_on_ragged_tiles(shape, rk4, restore_staged):
+def test_staged_forward_on_ragged_tiles(shape, rk4, weight, restore_staged):
     p = synth.blob_pair(shape, 454, max_disp=2.0, sigma=(1.5, 3.0))
     args = (t(p.M0), t(p.M1), t(p.MI0), t(p.MI1))
-    prm = L.Params(T=3, n_levels=1, iters=(3,), step=0.02, guard=False, weight=(1.0, 0.5),
+    prm = L.Params(T=3, n_levels=1, iters=(3,), step=0.02, guard=False, weight=weight,
                    flags=L.FLAG_RK4 if rk4 else 0)
     P = L.lddmm_comp_grid(shape, prm, 0, 0.05)
     assert P == shape
     v0 = t(0.05 * synth.random_velocity(P, 3, 124, vmax=3.0, sigma_s=2.0))
     out = {}
     for name, staged, tiles in (("grid", 1 << 30, 0), ("staged", 1, DEFAULT_TILES)):
-        say(f"forward traversal {name} on ragged tiles {shape}, rk4={rk4}")
+        say(f"forward traversal {name} on ragged tiles {shape}, rk4={rk4}, weight={weight}")
         L.lddmm_set_tunable(L.TUNE_FWD_TILES, tiles)
         L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, staged)
         r = L.lddmm_register(*args, params=prm, spacing=0.05, v=v0.clone())
@@ -200,16 +204,17 @@ def test_staged_forward_on_ragged_tiles(shape, rk4, restore_staged):
     assert torch.allclose(a["trace"][:, :3], b["trace"][:, :3], rtol=1e-12, atol=0.0)
 
 
-def test_staged_forward_energy_matches_the_oracle(restore_staged):
+@pytest.mark.parametrize("weight", [(1.0, 0.3), (1.0, 0.0)])
+def test_staged_forward_energy_matches_the_oracle(weight, restore_staged):
     h, T = 0.05, 4
     p = synth.blob_pair(SHAPE, 453, max_disp=2.0, sigma=(2.0, 4.0))
     P = tuple(O.smooth7(n) for n in SHAPE)
     v = (h * synth.random_velocity(P, T, 123, vmax=6.0, sigma_s=3.0)).astype(np.float32)
-    prm = O.Params(T=T, spacing=h, weight=(1.0, 0.3))
+    prm = O.Params(T=T, spacing=h, weight=weight)
     ref = O.energy(O.Problem(p.M0, p.M1, p.MI0, p.MI1), prm, v.astype(np.float64))
-    lp = L.Params(T=T, n_levels=1, iters=(0,), weight=(1.0, 0.3))
+    lp = L.Params(T=T, n_levels=1, iters=(0,), weight=weight)
     L.lddmm_set_tunable(L.TUNE_FWD_STAGED_MIN_BLOCKS, 1)
-    say("staged forward: energy vs oracle")
+    say(f"staged forward: energy vs oracle, weight={weight}")
     out = host(L.lddmm_energy(t(p.M0), t(p.M1), t(p.MI0), t(p.MI1), t(v), lp, spacing=h))
     for k, name in enumerate(("E", "R", "D", "img_ssd")):
         assert rel(out[k], ref[name]) < 1e-5, name
