@@ -627,7 +627,8 @@ __device__ __forceinline__ SlabTile slab_tile(const Geom& g, int block) {
 struct MapRing {
   float (*s)[3][kBYH][kBXH];     // [slot][component][row][column]
   float reg[kURegs];
-  uint32_t off[kURegs];          // in-plane element offset of element r, component included
+  uint32_t off[kURegs];          // in-plane element offset of element r, component included,
+                                 // of the periodic image of its (x, y)
   uint32_t ok;                   // bit r: element r lies in the grid's (x, y) range
   __device__ __forceinline__ void init(const Geom& g, uint32_t n, int x0, int y0) {
     ok = 0u;
@@ -639,10 +640,9 @@ struct MapRing {
         const int c = e / (kBYH * kBXH), rem = e - c * (kBYH * kBXH);
         const int ly = rem / kBXH, lx = rem - ly * kBXH;
         const int gx = x0 - kBH + lx, gy = y0 - kBH + ly;
-        if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny) {
-          off[r] = (uint32_t)c * n + (uint32_t)(gy * g.nx + gx);
-          ok |= 1u << r;
-        }
+        const int px = (gx % g.nx + g.nx) % g.nx, py = (gy % g.ny + g.ny) % g.ny;
+        off[r] = (uint32_t)c * n + (uint32_t)(py * g.nx + px);
+        if ((unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny) ok |= 1u << r;
       }
     }
   }
@@ -653,9 +653,27 @@ struct MapRing {
 #pragma unroll
     for (int r = 0; r < kURegs; ++r) reg[r] = (pin && ((ok >> r) & 1u)) ? bld(U, off[r] + po) : 0.f;
   }
+  // Plane p (-nz <= p < 2 nz) of a periodic field into registers, the window
+  // wrapped around the grid in x, y and z.
+  __device__ __forceinline__ void fetch_periodic(rsrc_t U, const Geom& g, int p) {
+    const int pw = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
+    const uint32_t po = (uint32_t)pw * (uint32_t)(g.nx * g.ny);
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r)
+      reg[r] = (threadIdx.x + r * kBlock < kUPlane) ? bld(U, off[r] + po) : 0.f;
+  }
+  // Plane p >= 0 into slot p mod 2 of a two-slot ring of the same window.
+  __device__ __forceinline__ void put2(int p) {
+    float* base = &s[p & 1][0][0][0];
+#pragma unroll
+    for (int r = 0; r < kURegs; ++r) {
+      const int e = threadIdx.x + r * kBlock;
+      if (e < kUPlane) base[e] = reg[r];
+    }
+  }
+  // Plane p >= -kBRing into slot (p + kBRing) mod kBRing.
   __device__ __forceinline__ void put(int p) {
-    if (p < 0) return;
-    float* base = &s[p % kBRing][0][0][0];
+    float* base = &s[(p + kBRing) % kBRing][0][0][0];
 #pragma unroll
     for (int r = 0; r < kURegs; ++r) {
       const int e = threadIdx.x + r * kBlock;
@@ -1022,26 +1040,35 @@ struct StagedTemplateSampler {
 
 template <int NC, bool FIRST, bool LAST, bool RK4>
 __device__ void forward_staged_body(const FwdArgs& a, int block) {
-  // The template channel is staged too in the first-order steps that are not the
-  // last, with one weighted channel (the last step, the RK4 steps and a second
-  // channel hold more live registers, and the ring would cost a wave per SIMD).
+  // v_j is staged as well: planes z and z + 1 of its periodic extension in two
+  // slots, the in-plane neighbours of the 7-point stencil and its z + 1 term
+  // (the z - 1 term is the previous step's centre).  The template channel is staged too in the
+  // first-order steps that are not the last, with one weighted channel (the last
+  // step, the RK4 steps and a second channel hold more live registers, and the
+  // ring would cost a wave per SIMD).
+  static_assert(kBH == 1, "the v window is the map window");
   constexpr bool TR = NC == 1 && !LAST && !RK4;
-  constexpr bool SYNC = !FIRST || TR;                         // a ring to fill
   __shared__ float su[kBRing][3][kBYH][kBXH];
+  __shared__ float sv[2][3][kBYH][kBXH];
   __shared__ float stp[TR ? 3 : 1][NC][kBYJ][kBXJ];
   if (a.st->mode == MODE_STOPPED) return;                     // uniform over the grid
   const Geom g = a.g;
   const FwdView<NC> f = fwd_view<NC, LAST>(a);
   const uint32_t n = (uint32_t)g.n;
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int nx = g.nx, ny = g.ny;
   const uint32_t nxy = (uint32_t)(nx * ny);
   const SlabTile tt = slab_tile(g, block);
   const int tx = threadIdx.x % kBX, ty = threadIdx.x / kBX;
   const int x = tt.x0 + tx, y = tt.y0 + ty;
   const bool inside = x < nx && y < ny;
-  MapRing mu;
+  const int lx = tx + 1, ly = ty + 1;                         // own position in the windows
+  MapRing mu, vr;
   mu.s = su;
+  vr.s = sv;
+  vr.init(g, n, tt.x0, tt.y0);
   const rsrc_t U = rsrc(a.u_cur, 3u * n);
+  const float* vb = (a.st->eval ? a.vB : a.vA) + (long long)a.j * 3 * g.n;
+  const rsrc_t VA = rsrc(vb, 3u * n);                         // all three components
   if (!FIRST) {
     mu.init(g, n, tt.x0, tt.y0);
     for (int q = tt.zbeg - kBH; q < tt.zbeg + kBH; ++q) {
@@ -1049,6 +1076,15 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
       mu.put(q);
     }
     mu.fetch(U, g, tt.zbeg + kBH);
+  }
+  vr.fetch_periodic(VA, g, tt.zbeg);
+  vr.put2(tt.zbeg);
+  vr.fetch_periodic(VA, g, tt.zbeg + 1);
+  float vm[3] = {0.f, 0.f, 0.f};                              // v_j of plane z - 1 at (x, y)
+  if (inside) {
+    const uint32_t zb = tt.zbeg == 0 ? (uint32_t)g.nz - 1 : (uint32_t)tt.zbeg - 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vm[c] = bld(VA, (uint32_t)c * n + zb * nxy + (uint32_t)(y * nx + x));
   }
   HaloRing<NC> rt;                                            // template planes z - 1 .. z + 1
   if constexpr (TR) {
@@ -1063,47 +1099,29 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
     }
     rt.fetch(f.T0, g, tt.zbeg + 1);
   }
-  // periodic in-plane neighbours as offsets added to i (modulo 2^32)
   const uint32_t p = inside ? (uint32_t)(y * nx + x) : 0u;
-  const uint32_t dxm = x == 0 ? (uint32_t)(nx - 1) : 0u - 1u;
-  const uint32_t dxp = x == nx - 1 ? 0u - (uint32_t)(nx - 1) : 1u;
-  const uint32_t dym = y == 0 ? (uint32_t)((ny - 1) * nx) : 0u - (uint32_t)nx;
-  const uint32_t dyp = y == ny - 1 ? 0u - (uint32_t)((ny - 1) * nx) : (uint32_t)nx;
-  const rsrc_t V[3] = {f.V0, f.V1, f.V2};
-  float vm[3] = {0.f, 0.f, 0.f}, vc[3] = {0.f, 0.f, 0.f}, vp[3] = {0.f, 0.f, 0.f};
-  uint32_t zp = tt.zbeg + 1 == nz ? 0u : (uint32_t)tt.zbeg + 1;
-  if (inside) {
-    const uint32_t zb = tt.zbeg == 0 ? (uint32_t)nz - 1 : (uint32_t)tt.zbeg - 1;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      vm[c] = bld(V[c], zb * nxy + p);
-      vc[c] = bld(V[c], (uint32_t)tt.zbeg * nxy + p);
-      vp[c] = bld(V[c], zp * nxy + p);
-    }
-  }
   const StagedMapSampler<NC> ms{mu, f, g, tt.x0, tt.y0};
   double accR = 0.0, accD = 0.0, accI = 0.0;
   for (int z = tt.zbeg; z < tt.zend; ++z) {
     if (!FIRST) mu.put(z + kBH);
+    vr.put2(z + 1);
     if (TR) rt.put(z + 1);
-    if (SYNC) __syncthreads();
+    __syncthreads();
     if (z + 1 < tt.zend) {                                    // in flight during the step
       if (!FIRST) mu.fetch(U, g, z + kBH + 1);
+      vr.fetch_periodic(VA, g, z + 2);
       if (TR) rt.fetch(f.T0, g, z + 2);
     }
-    const uint32_t zn = zp + 1 == (uint32_t)nz ? 0u : zp + 1;  // the plane after next
     if (inside) {
       const uint32_t i = (uint32_t)z * nxy + p;
-      float vn[3] = {0.f, 0.f, 0.f};
-      if (z + 1 < tt.zend) {
+      const int s0 = z & 1, sp = s0 ^ 1;
+      float vc[3], lap[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vn[c] = bld(V[c], zn * nxy + p);
+      for (int c = 0; c < 3; ++c) {
+        vc[c] = sv[s0][c][ly][lx];
+        lap[c] = lap7_of(sv[s0][c][ly][lx - 1], sv[s0][c][ly][lx + 1], sv[s0][c][ly - 1][lx],
+                         sv[s0][c][ly + 1][lx], vm[c], sv[sp][c][ly][lx], vc[c]);
       }
-      float lap[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        lap[c] = lap7_of(bld(V[c], i + dxm), bld(V[c], i + dxp), bld(V[c], i + dym),
-                         bld(V[c], i + dyp), vm[c], vp[c], vc[c]);
       if constexpr (TR)
         forward_voxel<NC, FIRST, LAST, RK4>(a, f, i, x, y, z, vc[0], vc[1], vc[2], lap[0], lap[1],
                                             lap[2], accR, accD, accI, ms,
@@ -1113,14 +1131,9 @@ __device__ void forward_staged_body(const FwdArgs& a, int block) {
                                             lap[2], accR, accD, accI, ms,
                                             GlobalTemplateSampler<NC>{f, g});
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        vm[c] = vc[c];
-        vc[c] = vp[c];
-        vp[c] = vn[c];
-      }
+      for (int c = 0; c < 3; ++c) vm[c] = vc[c];
     }
-    zp = zn;
-    if (SYNC) __syncthreads();
+    __syncthreads();
   }
   forward_partials<LAST>(a, (uint32_t)block, accR, accD, accI);
 }
