@@ -378,10 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) 
   const int p = batch_pair(br, blockIdx.x);
   const PairTab* t = (const PairTab*)br.tab[p];
   const uint32_t tile = blockIdx.x - br.off[p], ntiles = br.off[p + 1] - br.off[p];
-  if (t->fwd[j].staged && !(FIRST && !LAST))
+  if (t->fwd[j].staged)
     forward_staged_body<NC, FIRST, LAST, false>(t->fwd[j], (int)tile);
-  else if (t->fwd[j].staged || t->fwd[j].zmarch)
-    forward_zmarch_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);   // as fwd_dispatch
+  else if (t->fwd[j].zmarch)
+    forward_zmarch_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
   else
     forward_body<NC, FIRST, LAST>(t->fwd[j], tile, ntiles);
 }
@@ -424,10 +424,7 @@ static void fwd_dispatch(const FwdArgs& a, hipStream_t s) {
 #define FWD(F, L, Z) \
   hipLaunchKernelGGL((k_forward<NC, F, L, RK4, Z>), dim3(grid), dim3(kBlock), 0, s, a)
   if (a.staged) {
-    // the first step has no map to gather: plane-marching over the same tile
-    // count (a multiple of 8) is faster there (129 against 139 us at the finest
-    // atlas level) and writes the same partial slots
-    if (first && last) FWD(true, true, 2); else if (first) FWD(true, false, 1);
+    if (first && last) FWD(true, true, 2); else if (first) FWD(true, false, 2);
     else if (last) FWD(false, true, 2); else FWD(false, false, 2);
   } else if (a.zmarch) {
     if (first && last) FWD(true, true, 1); else if (first) FWD(true, false, 1);
