@@ -421,6 +421,14 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
                                         component where the separate passes pack
                                         rows across components, so K b differs in
                                         rounding only (FP32). */
+#define LDDMM_TUNE_K_TIME_BATCH 8   /* 1 (default): on the levels of lddmm_register
+                                        with at most 2^21 voxels, the backward sweep
+                                        keeps the T body forces and then applies K
+                                        and the update to all of them, one launch
+                                        per pass; 0: K and the update after each
+                                        step.  Same results; the workspace holds the
+                                        buffers either way.  Values other than 0
+                                        and 1: LDDMM_EINVAL. */
 int lddmm_set_tunable(int32_t which, int32_t value);
 
 /* Device copy of n floats, src -> dst (device, not overlapping): the library's

@@ -116,6 +116,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t state, partR, partD, partI, partDet, trace, tw[3], lam[3];
   size_t J0, J1, v0, v1, u0, u1, J0t, r, b, S, ub, misc, ptab, total;
+  size_t bT, ST, ttab;             // time-batched K: T body forces, spectra, tables (0: none)
   size_t Joff[LDDMM_MAX_LEVELS];   // per-level offsets (floats) inside J0 / J1
   int n_u0;                         // u0 slots
 };
@@ -128,7 +129,18 @@ struct Config {
   int rows;
   int ck;            // exact gradient: checkpoint spacing (0 = keep every u0_j)
   int rk4;           // departure points by fourth-order Runge-Kutta (LDDMM_FLAG_RK4)
+  int kt_mask;       // bit li: level li of a descent smooths its T body forces in one batch
 };
+
+// Levels of a descent whose K passes run over all T time steps at once: up to
+// this many voxels a level's passes are short and bound by the latency of one
+// block's phases (a 140 x 80 x 120 pass has 360 blocks for 256 CUs), and ten
+// times the blocks fill the chip.  The finest atlas level (10.75 M voxels)
+// fills it alone.
+constexpr long long kTimeBatchMaxVoxels = 1LL << 21;
+static int g_k_time_batch = 1;
+
+static void set_k_time_batch(int on) { g_k_time_batch = on ? 1 : 0; }
 
 // u0 storage of the exact gradient.  Without recompute slot j holds u0_j.  With
 // checkpoints every ck steps: slots [0, nck) hold u0 at j = 0, ck, 2 ck, ... and
@@ -216,6 +228,10 @@ static int make_config(const lddmm_grid* grid, const lddmm_params* p, int has_im
   c->ck = (p->flags & LDDMM_FLAG_RECOMPUTE_PHI) ? (p->checkpoint_every > 0 ? p->checkpoint_every
                                                                             : 1)
                                                 : 0;
+  c->kt_mask = 0;
+  if (multilevel)
+    for (int l = 0; l < c->L; ++l)
+      if (c->lv[l].g.n <= kTimeBatchMaxVoxels) c->kt_mask |= 1 << l;
   return LDDMM_OK;
 }
 
@@ -258,6 +274,18 @@ static Layout make_layout(const Config& c) {
   o.ub = take(sizeof(float) * 3 * n * 2);
   o.misc = take(sizeof(int) * 64);
   o.ptab = take(sizeof(PairTab));
+  o.bT = o.ST = o.ttab = 0;
+  if (c.kt_mask) {
+    size_t nmax = 0, smax = 0;
+    for (int l = 0; l < c.L; ++l)
+      if ((c.kt_mask >> l) & 1) {
+        nmax = std::max(nmax, (size_t)c.lv[l].g.n);
+        smax = std::max(smax, (size_t)c.lv[l].g.nspec);
+      }
+    o.bT = take(sizeof(float) * 3 * nmax * c.T);
+    o.ST = take(sizeof(float2) * 3 * smax * c.T);
+    o.ttab = take(sizeof(PairTab) * c.T);
+  }
   o.total = align_up(off);
   return o;
 }
@@ -277,6 +305,14 @@ struct Ctx {
   float2* S;
   double alpha, gamma, sigma;
   int guard;
+  // time-batched K (levels in cfg.kt_mask): body forces [T][3][n], spectra
+  // [T][3][nspec], one device table per time step and the host copy behind it
+  float* bT;
+  float2* ST;
+  PairTab* ttab;
+  std::vector<PairTab> htab;
+  int ttab_level;
+  UpdArgs ttab_upd;
 };
 
 static void bind(Ctx& c, void* ws) {
@@ -305,6 +341,10 @@ static void bind(Ctx& c, void* ws) {
   c.ub = (float*)(c.ws + o.ub);
   c.misc = (int*)(c.ws + o.misc);
   c.ptab = (PairTab*)(c.ws + o.ptab);
+  c.bT = o.bT ? (float*)(c.ws + o.bT) : nullptr;
+  c.ST = o.ST ? (float2*)(c.ws + o.ST) : nullptr;
+  c.ttab = o.ttab ? (PairTab*)(c.ws + o.ttab) : nullptr;
+  c.ttab_level = -1;
 }
 
 static void level_tables(Ctx& c, const Level& L, hipStream_t s) {
@@ -421,14 +461,78 @@ static void smooth_and_update(Ctx& c, int li, const UpdArgs& u, int need_mode, h
   }
 }
 
+// K b_j and the epilogue of every time step j at once, from the body forces
+// b_j in c.bT: the batched passes with one table per time step (its FftPair on
+// b_j and the j-th slice of c.ST, its epilogue in upd[0]).  The per-line
+// arithmetic is that of the single-step launches, so the results are the same
+// bits.  The tables are written once per level and epilogue.
+static void smooth_and_update_all(Ctx& c, int li, const UpdArgs& u, int need_mode,
+                                  hipStream_t s) {
+  const Config& k = c.cfg;
+  const long long n = k.lv[li].g.n;
+  FftLaunch L;
+  const FftPair f = make_fft(c, li, need_mode, &L);
+  const UpdArgs& t = c.ttab_upd;
+  if (c.ttab_level != li || t.kind != u.kind || t.vA != u.vA || t.vB != u.vB ||
+      t.vfix != u.vfix || t.out != u.out || t.need_mode != u.need_mode) {
+    c.htab.assign(k.T, PairTab{});
+    for (int j = 0; j < k.T; ++j) {
+      PairTab& h = c.htab[j];
+      h.fft = f;
+      h.fft.b = c.bT + (long long)j * 3 * n;
+      h.fft.S = c.ST + (long long)j * 3 * f.g.nspec;
+      h.upd[0] = u;
+      h.upd[0].j = j;
+    }
+    hipMemcpyAsync(c.ttab, c.htab.data(), sizeof(PairTab) * k.T, hipMemcpyHostToDevice, s);
+    c.ttab_level = li;
+    c.ttab_upd = u;
+  }
+  for (int j0 = 0; j0 < k.T; j0 += kMaxBatch) {
+    const int np = std::min(kMaxBatch, k.T - j0);
+    BatchRef bx{}, by{}, bz{};
+    bx.np = by.np = bz.np = np;
+    for (int p = 0; p <= np; ++p) {
+      bx.off[p] = p * L.x_tiles;
+      by.off[p] = p * L.y_tiles;
+      bz.off[p] = p * L.z_tiles;
+    }
+    for (int p = 0; p < np; ++p) bx.tab[p] = by.tab[p] = bz.tab[p] = c.ttab + j0 + p;
+    {
+      ProfScope ps(LDDMM_PROF_FFT_X, n, s);
+      launch_fft_batched(0, bx, L.ex, L.x_lds, 0, s);
+    }
+    if (!f.fused) {
+      ProfScope ps(LDDMM_PROF_FFT_Y, n, s);
+      launch_fft_batched(1, by, L.ey, L.y_lds, 0, s);
+    }
+    {
+      ProfScope ps(LDDMM_PROF_FFT_ZK, n, s);
+      launch_fft_batched(2, bz, L.ez, L.z_lds, 0, s);
+    }
+    if (!f.fused) {
+      ProfScope ps(LDDMM_PROF_FFT_YINV, n, s);
+      launch_fft_batched(3, by, L.ey, L.y_lds, 0, s);
+    }
+    {
+      ProfScope ps(LDDMM_PROF_FFT_XINV, n, s);
+      launch_fft_batched(4, bx, L.ex, L.x_lds, 0, s);
+    }
+  }
+}
+
 // Backward sweep: maps u1_j, body forces b_j, K b_j and the epilogue per j.
 // With with_grad = false only the maps are computed (u1_0 ends in slot 0).
+// With time_batch, every b_j goes to its own slice of c.bT and K and the
+// epilogue of all time steps follow the sweep (the sweep reads the iterate
+// that the epilogue does not write, so the order changes nothing).
 static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vfix, bool with_grad,
                            int upd_kind, float* gout, int need_mode, hipStream_t s,
-                           bool smooth = true) {
+                           bool smooth = true, bool time_batch = false) {
   const Config& k = c.cfg;
   const Level& L = k.lv[li];
   const long long n = L.g.n;
+  time_batch = time_batch && with_grad && smooth && c.bT != nullptr && ((k.kt_mask >> li) & 1);
   for (int j = k.T - 1; j >= (with_grad ? -1 : 0); --j) {
     BwdArgs a{};
     a.g = L.g;
@@ -454,7 +558,7 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
     a.w[0] = k.w[0];
     a.w[1] = k.nch > 1 ? k.w[1] : 0.f;
     a.coef = (float)(2.0 / (c.sigma * c.sigma));
-    a.b = c.b;
+    a.b = (time_batch && a.jb >= 0) ? c.bT + (long long)a.jb * 3 * n : c.b;
     a.partDet = c.partDet + (long long)(a.jb >= 0 ? a.jb : 0) * kPartMax;
     a.st = c.st;
     a.need_mode = need_mode;
@@ -467,7 +571,7 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
       ProfScope ps(both ? LDDMM_PROF_BACKWARD : LDDMM_PROF_BACKWARD_EDGE, n, s);
       launch_backward(a, s);
     }
-    if (a.jb >= 0 && smooth) {
+    if (a.jb >= 0 && smooth && !time_batch) {
       UpdArgs u{};
       u.kind = upd_kind;
       u.j = a.jb;
@@ -479,6 +583,17 @@ static void backward_sweep(Ctx& c, int li, float* vA, float* vB, const float* vf
       u.need_mode = need_mode;
       smooth_and_update(c, li, u, need_mode, s);
     }
+  }
+  if (time_batch) {
+    UpdArgs u{};
+    u.kind = upd_kind;
+    u.vA = vA;
+    u.vB = vB;
+    u.vfix = vfix;
+    u.out = gout;
+    u.st = c.st;
+    u.need_mode = need_mode;
+    smooth_and_update_all(c, li, u, need_mode, s);
   }
 }
 
@@ -753,7 +868,8 @@ int lddmm_register(lddmm_problem* p, int32_t n_problems, const lddmm_params* prm
     forward_sweep(c, li, c.v[0], c.v[1], false, s);
     decide(c, li, 1, trace, s);
     for (int it = 0; it < prm->iters[li]; ++it) {
-      backward_sweep(c, li, c.v[0], c.v[1], nullptr, true, UPD_STEP, nullptr, MODE_GRAD, s);
+      backward_sweep(c, li, c.v[0], c.v[1], nullptr, true, UPD_STEP, nullptr, MODE_GRAD, s, true,
+                     g_k_time_batch != 0);
       {
         ProfScope ps(LDDMM_PROF_OTHER, 0, s);
         launch_retry(c.v[0], c.v[1], 3 * L.g.n * k.T, c.st, s);
@@ -1242,6 +1358,11 @@ int lddmm_set_tunable(int32_t which, int32_t value) {
   if (which == LDDMM_TUNE_FFT_FUSED_LDS) {
     if (value < 0) return LDDMM_EINVAL;
     set_fft_fused_lds(value);
+    return LDDMM_OK;
+  }
+  if (which == LDDMM_TUNE_K_TIME_BATCH) {
+    if (value < 0 || value > 1) return LDDMM_EINVAL;
+    set_k_time_batch(value);
     return LDDMM_OK;
   }
   if (which == LDDMM_TUNE_FFT_X_ELEMS) {

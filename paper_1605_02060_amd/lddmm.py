@@ -160,6 +160,7 @@ TUNE_STAGED_MIN_BLOCKS = 4
 TUNE_FWD_TILES = 5
 TUNE_FWD_STAGED_MIN_BLOCKS = 6
 TUNE_FFT_FUSED_LDS = 7
+TUNE_K_TIME_BATCH = 8
 
 PROF_CLASSES = ["forward", "backward", "fft_x", "fft_y", "fft_zK", "fft_yinv", "fft_xinv_update",
                 "other", "hist_range", "hist_count", "hist_apply", "align", "forward_edge",

@@ -189,6 +189,10 @@ static void tunables_strings_profile() {
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_FUSED_LDS, -1) == LDDMM_EINVAL);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_FUSED_LDS, 0) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_FUSED_LDS, 81920) == LDDMM_OK);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_K_TIME_BATCH, -1) == LDDMM_EINVAL);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_K_TIME_BATCH, 2) == LDDMM_EINVAL);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_K_TIME_BATCH, 0) == LDDMM_OK);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_K_TIME_BATCH, 1) == LDDMM_OK);
   CHECK(lddmm_set_tunable(99, 1) == LDDMM_EINVAL);
   CHECK(lddmm_set_tunable(-1, 1) == LDDMM_EINVAL);
   // back to the defaults

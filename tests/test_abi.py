@@ -112,7 +112,7 @@ def test_tunable_ids_match_header_and_values_are_checked():
     from paper_1605_02060_amd import tune
     src = open(os.path.join(ROOT, "include", "lddmm.h")).read()
     for name in ("SWEEP_BLOCKS", "FFT_X_ELEMS", "FFT_COLS", "FFT_ZCOLS", "STAGED_MIN_BLOCKS",
-                 "FWD_TILES", "FWD_STAGED_MIN_BLOCKS", "FFT_FUSED_LDS"):
+                 "FWD_TILES", "FWD_STAGED_MIN_BLOCKS", "FFT_FUSED_LDS", "K_TIME_BATCH"):
         val = int(re.search(rf"#define LDDMM_TUNE_{name}\s+(\d+)", src).group(1))
         assert getattr(L, f"TUNE_{name}") == val
     assert set(tune.DEFAULTS) == set(tune.CANDIDATES) == set(tune.NAMES)
@@ -127,6 +127,11 @@ def test_tunable_ids_match_header_and_values_are_checked():
             L.lddmm_set_tunable(L.TUNE_FFT_FUSED_LDS, -1)
         L.lddmm_set_tunable(L.TUNE_FFT_FUSED_LDS, 0)       # 0: never fuse
         L.lddmm_set_tunable(L.TUNE_FFT_FUSED_LDS, 81920)
+        for bad in (-1, 2):
+            with pytest.raises(RuntimeError):
+                L.lddmm_set_tunable(L.TUNE_K_TIME_BATCH, bad)
+        L.lddmm_set_tunable(L.TUNE_K_TIME_BATCH, 0)        # K after each step
+        L.lddmm_set_tunable(L.TUNE_K_TIME_BATCH, 1)
         L.lddmm_set_tunable(L.TUNE_FWD_TILES, 0)          # 0: the grid-stride forward sweep
         L.lddmm_set_tunable(L.TUNE_FWD_TILES, 1 << 20)    # clamped to the partial buffers
     finally:
