@@ -89,7 +89,13 @@ def _run_once(pairs, params, wss):
         L.lddmm_register_batched(pairs, params, wss=wss, want_phi=False)
 
 
-def autotune(pairs, params: L.Params, iters=3, repeats=2, use_cache=True, verbose=False):
+# A candidate replaces the current value only when it is at least this much
+# faster: trial times of a few iterations vary by about 1 % from run to run, and
+# the plain minimum then picked shapes that were slower over a whole registration.
+MARGIN = 0.01
+
+
+def autotune(pairs, params: L.Params, iters=3, repeats=3, use_cache=True, verbose=False):
     """Pick the fastest launch shapes for these problems (list of dicts with M0, M1,
     optional MI0, MI1, spacing).  Returns {tunable id: value}; leaves them set."""
     shapes = [tuple(d["M0"].shape) for d in pairs]
@@ -123,12 +129,14 @@ def autotune(pairs, params: L.Params, iters=3, repeats=2, use_cache=True, verbos
         return best
 
     for which, values in CANDIDATES.items():
+        current = choice[which]
         times = {}
-        for v in values:
+        for v in (current,) + tuple(x for x in values if x != current):
             choice[which] = v
             set_all(choice)
             times[v] = timed()
-        choice[which] = min(times, key=times.get)
+        best = min(times, key=times.get)
+        choice[which] = best if times[best] < (1.0 - MARGIN) * times[current] else current
         if verbose:
             print(NAMES[which], {v: round(t * 1e3, 3) for v, t in times.items()}, "->",
                   choice[which])
