@@ -93,7 +93,7 @@ def kernel_name(cls, tunables, rk4, nch=1):
     summaries name it), given the launch-shape choice."""
     b = lambda x: "true" if x else "false"
     if cls == "forward":
-        zm = tunables.get("fwd_tiles", 3584) > 0
+        zm = tunables.get("fwd_tiles", 1792) > 0
         return f"k_forward<{nch}, false, false, {b(rk4)}, {b(zm)}>"
     if cls == "backward":
         if tunables.get("staged_min_blocks", 2048) <= 3200:   # 3200 staged blocks at 280x160x240

@@ -380,7 +380,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * Launch-shape tunables (process-wide; results are identical for every value,
  * only speed changes).  LDDMM_TUNE_SWEEP_BLOCKS: blocks of the forward and
  * backward sweep kernels (rounded to a multiple of 8, clamped to [8, 4096];
- * default 1024).  LDDMM_TUNE_FFT_X_ELEMS: complex values one block of the x
+ * default 4096).  LDDMM_TUNE_FFT_X_ELEMS: complex values one block of the x
  * passes of K holds in LDS (row pairs per block = value / (3 nx), 1..8; clamped
  * to [256, 8192]; default 2048).  LDDMM_TUNE_FFT_COLS / LDDMM_TUNE_FFT_ZCOLS:
  * kx columns per tile of the y / the z pass (rounded down to a power of two in
@@ -391,7 +391,7 @@ int lddmm_profile_end(double *ms_total, int64_t *launches, int64_t *voxels);
  * forward sweep gives each thread a column of one xy plane block (256 voxels)
  * and a run of consecutive z-planes, with at most this many blocks where that
  * allows one run per plane block (whole runs, rounded up to a multiple of 8, at
- * most 4096; default 3584), on grids whose xy plane needs
+ * most 4096; default 1792), on grids whose xy plane needs
  * at most 4089 such blocks; 0 selects the grid-stride forward sweep with
  * LDDMM_TUNE_SWEEP_BLOCKS blocks on every grid.  Block counts and traversals
  * change only the order of the FP64 energy partial sums.  A value applies to

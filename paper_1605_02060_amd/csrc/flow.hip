@@ -13,7 +13,7 @@
 namespace lddmm {
 
 // Blocks of a sweep kernel: a multiple of the 8 XCDs, at most g_sweep_blocks.
-static int g_sweep_blocks = 1024;
+static int g_sweep_blocks = 4096;
 
 void set_sweep_blocks(int b) {
   b = (b + kXCD - 1) / kXCD * kXCD;
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_batched(BatchRef br, int j) 
 // Tiles of a plane-marching launch: whole runs of planes for every plane block,
 // at most g_fwd_tiles where that allows one run, rounded up to a multiple of 8;
 // 0 selects the grid-stride traversal.
-static int g_fwd_tiles = 3584;
+static int g_fwd_tiles = 1792;
 
 void set_fwd_tiles(int t) { g_fwd_tiles = t <= 0 ? 0 : (t > kPartMax ? kPartMax : t); }
 

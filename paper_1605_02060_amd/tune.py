@@ -19,7 +19,7 @@ import torch
 
 from . import lddmm as L
 
-DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 1024, L.TUNE_FWD_TILES: 3584, L.TUNE_STAGED_MIN_BLOCKS: 2048,
+DEFAULTS = {L.TUNE_SWEEP_BLOCKS: 4096, L.TUNE_FWD_TILES: 1792, L.TUNE_STAGED_MIN_BLOCKS: 2048,
             L.TUNE_FFT_X_ELEMS: 2048, L.TUNE_FFT_COLS: 16, L.TUNE_FFT_ZCOLS: 8,
             L.TUNE_FWD_STAGED_MIN_BLOCKS: 2048}
 CANDIDATES = {

@@ -196,12 +196,12 @@ static void tunables_strings_profile() {
   CHECK(lddmm_set_tunable(99, 1) == LDDMM_EINVAL);
   CHECK(lddmm_set_tunable(-1, 1) == LDDMM_EINVAL);
   // back to the defaults
-  CHECK(lddmm_set_tunable(LDDMM_TUNE_SWEEP_BLOCKS, 1024) == LDDMM_OK);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_SWEEP_BLOCKS, 4096) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_X_ELEMS, 2048) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_COLS, 16) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FFT_ZCOLS, 8) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_STAGED_MIN_BLOCKS, 2048) == LDDMM_OK);
-  CHECK(lddmm_set_tunable(LDDMM_TUNE_FWD_TILES, 3584) == LDDMM_OK);
+  CHECK(lddmm_set_tunable(LDDMM_TUNE_FWD_TILES, 1792) == LDDMM_OK);
   CHECK(lddmm_set_tunable(LDDMM_TUNE_FWD_STAGED_MIN_BLOCKS, 2048) == LDDMM_OK);
   for (int code = -10; code <= 10; ++code) {
     const char* s = lddmm_strerror(code);

@@ -23,7 +23,7 @@ from paper_1605_02060_amd import synth
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
-DEFAULT_TILES = 3584
+DEFAULT_TILES = 1792
 
 
 def say(msg):
@@ -64,8 +64,8 @@ def test_traversals_give_the_same_registration(rk4, restore_tiles):
     out = {}
     # on the finest grid -- 0: grid-stride; 1: 8 tiles, one run of all 30 planes
     # per plane block; 16: runs of 15; 32: runs of 8 with a ragged last run of 6;
-    # 3584 (the default): one plane per run
-    for tiles in (0, 1, 16, 32, DEFAULT_TILES):
+    # 3584: one plane per run; 1792, the default
+    for tiles in (0, 1, 16, 32, 3584, DEFAULT_TILES):
         say(f"forward tiles {tiles} rk4={rk4}")
         L.lddmm_set_tunable(L.TUNE_FWD_TILES, tiles)
         r = L.lddmm_register(*args, params=prm, spacing=0.05)
