@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <list>
 #include <vector>
 
 #include "internal.h"
@@ -306,11 +307,13 @@ struct Ctx {
   double alpha, gamma, sigma;
   int guard;
   // time-batched K (levels in cfg.kt_mask): body forces [T][3][n], spectra
-  // [T][3][nspec], one device table per time step and the host copy behind it
+  // [T][3][nspec], one device table per time step, and the host copies behind
+  // them (one set per table build, kept until the call returns, so that no
+  // copy still in flight reads a buffer that is being rewritten)
   float* bT;
   float2* ST;
   PairTab* ttab;
-  std::vector<PairTab> htab;
+  std::list<std::vector<PairTab>> htab;
   int ttab_level;
   UpdArgs ttab_upd;
 };
@@ -475,16 +478,16 @@ static void smooth_and_update_all(Ctx& c, int li, const UpdArgs& u, int need_mod
   const UpdArgs& t = c.ttab_upd;
   if (c.ttab_level != li || t.kind != u.kind || t.vA != u.vA || t.vB != u.vB ||
       t.vfix != u.vfix || t.out != u.out || t.need_mode != u.need_mode) {
-    c.htab.assign(k.T, PairTab{});
+    std::vector<PairTab>& ht = c.htab.emplace_back(k.T, PairTab{});
     for (int j = 0; j < k.T; ++j) {
-      PairTab& h = c.htab[j];
+      PairTab& h = ht[j];
       h.fft = f;
       h.fft.b = c.bT + (long long)j * 3 * n;
       h.fft.S = c.ST + (long long)j * 3 * f.g.nspec;
       h.upd[0] = u;
       h.upd[0].j = j;
     }
-    hipMemcpyAsync(c.ttab, c.htab.data(), sizeof(PairTab) * k.T, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(c.ttab, ht.data(), sizeof(PairTab) * k.T, hipMemcpyHostToDevice, s);
     c.ttab_level = li;
     c.ttab_upd = u;
   }
