@@ -880,7 +880,8 @@ __device__ __forceinline__ void ctx_inv_body(const FftPair& f, const UpdArgs& u,
 #define LDDMM_FUSED_PLANS(X) \
   X(140, 14, 10, 80, 10, 8) X(70, 10, 7, 40, 8, 5) X(32, 8, 4, 32, 8, 4) X(64, 8, 8, 64, 8, 8)
 
-constexpr int kFusedBlock = 512;   // threads of a single-problem launch (batched: kBlock)
+constexpr int kFusedBlock = 512;   // threads of a single-problem or time-batched launch
+                                    // (batches of several problems: kBlock)
 constexpr int kFusedBatch = 8;     // global loads in flight per thread in the row loops
 
 // LDS of the fused passes: the plane, then the x and y twiddles.
@@ -1146,6 +1147,26 @@ template <int NX1, int NX2, int NY1, int NY2>
 __global__ __launch_bounds__(kFusedBlock) void k_fftf_yx(FftPair f, UpdArgs u) {
   if (!gate(u.st, u.need_mode)) return;
   fused_inv_body<NX1, NX2, NY1, NY2>(f, u, (int)blockIdx.x / f.g.nz, (int)blockIdx.x % f.g.nz);
+}
+
+// The fused passes of a batch whose problems share one fused plan (the time steps
+// of one level), with the single-problem launch's kFusedBlock threads per block.
+template <int NX1, int NX2, int NY1, int NY2>
+__global__ __launch_bounds__(kFusedBlock) void k_fftf_xy_batched(BatchRef br) {
+  const int p = batch_pair(br, blockIdx.x);
+  const FftPair& f = ((const PairTab*)br.tab[p])->fft;
+  if (!gate(f.st, f.need_mode)) return;
+  const int b = (int)blockIdx.x - br.off[p];
+  fused_fwd_body<NX1, NX2, NY1, NY2>(f, b / f.g.nz, b % f.g.nz);
+}
+
+template <int NX1, int NX2, int NY1, int NY2>
+__global__ __launch_bounds__(kFusedBlock) void k_fftf_yx_batched(BatchRef br, int j) {
+  const int p = batch_pair(br, blockIdx.x);
+  const PairTab* t = (const PairTab*)br.tab[p];
+  if (!gate(t->upd[j].st, t->upd[j].need_mode)) return;
+  const int b = (int)blockIdx.x - br.off[p];
+  fused_inv_body<NX1, NX2, NY1, NY2>(t->fft, t->upd[j], b / t->fft.g.nz, b % t->fft.g.nz);
 }
 
 static bool fused_plan(int nx, int ny) {
@@ -1741,6 +1762,28 @@ void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hi
     hipLaunchKernelGGL(k_fft_x_inv<8>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u),
     hipLaunchKernelGGL(k_fft_x_inv<16>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u),
     hipLaunchKernelGGL(k_fft_x_inv<32>, dim3(L.x_tiles), dim3(kBlock), L.x_lds, s, f, u));
+}
+
+// Fused x + y passes of a batch whose problems all have grid g's fused plan
+// (inverse: the y-inverse and x-inverse pass with epilogue upd[j]).  Returns false,
+// launching nothing, when g has no fused plan.
+bool launch_fft_fused_batched(int inverse, const BatchRef& br, const Geom& g, size_t lds, int j,
+                              hipStream_t s) {
+  if (br.off[br.np] == 0) return true;
+  const dim3 grid(br.off[br.np]);
+#define LDDMM_FUSED_CASE(NX, A, B, NY, C, D)                                                  \
+  if (g.nx == NX && g.ny == NY) {                                                           \
+    if (inverse)                                                                            \
+      hipLaunchKernelGGL((k_fftf_yx_batched<A, B, C, D>), grid, dim3(kFusedBlock), lds, s,  \
+                         br, j);                                                            \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_fftf_xy_batched<A, B, C, D>), grid, dim3(kFusedBlock), lds, s,  \
+                         br);                                                               \
+    return true;                                                                            \
+  }
+  LDDMM_FUSED_PLANS(LDDMM_FUSED_CASE)
+#undef LDDMM_FUSED_CASE
+  return false;
 }
 
 // Batched passes: every problem of the batch in one launch (register budget and

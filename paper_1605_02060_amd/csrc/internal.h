@@ -266,6 +266,8 @@ void launch_fft_y(const FftPair& f, const FftLaunch& L, int inverse, hipStream_t
 void launch_fft_z_K(const FftPair& f, const FftLaunch& L, hipStream_t s);
 void launch_fft_x_inv(const FftPair& f, const FftLaunch& L, const UpdArgs& u, hipStream_t s);
 void launch_fft_batched(int pass, const BatchRef& br, int emax, size_t lds, int j, hipStream_t s);
+bool launch_fft_fused_batched(int inverse, const BatchRef& br, const Geom& g, size_t lds, int j,
+                              hipStream_t s);
 
 // grad.hip
 struct GradArgs {

@@ -501,9 +501,11 @@ static void smooth_and_update_all(Ctx& c, int li, const UpdArgs& u, int need_mod
       bz.off[p] = p * L.z_tiles;
     }
     for (int p = 0; p < np; ++p) bx.tab[p] = by.tab[p] = bz.tab[p] = c.ttab + j0 + p;
+    // fused x + y passes with the single-problem launch's block size
     {
       ProfScope ps(LDDMM_PROF_FFT_X, n, s);
-      launch_fft_batched(0, bx, L.ex, L.x_lds, 0, s);
+      if (!(f.fused && launch_fft_fused_batched(0, bx, f.g, L.x_lds, 0, s)))
+        launch_fft_batched(0, bx, L.ex, L.x_lds, 0, s);
     }
     if (!f.fused) {
       ProfScope ps(LDDMM_PROF_FFT_Y, n, s);
@@ -519,7 +521,8 @@ static void smooth_and_update_all(Ctx& c, int li, const UpdArgs& u, int need_mod
     }
     {
       ProfScope ps(LDDMM_PROF_FFT_XINV, n, s);
-      launch_fft_batched(4, bx, L.ex, L.x_lds, 0, s);
+      if (!(f.fused && launch_fft_fused_batched(1, bx, f.g, L.x_lds, 0, s)))
+        launch_fft_batched(4, bx, L.ex, L.x_lds, 0, s);
     }
   }
 }
