@@ -40,8 +40,10 @@ def common_flags():
 CONTRACT_ON = {"flow.hip", "fft.hip"}
 # Sources whose FP64 arithmetic restates a definition operation by operation
 # (histogram quantiles and the intensity map; affine sampling positions, where
-# a whole-number position must stay whole): no multiply-add fusion at all.
-CONTRACT_OFF = {"hist.hip", "align.hip"}
+# a whole-number position must stay whole; the guard's energies E = R + D, whose
+# rounding otherwise followed the compiler's fusion choice for the surrounding
+# code): no multiply-add fusion at all.
+CONTRACT_OFF = {"hist.hip", "align.hip", "control.hip"}
 
 
 def flags_for(src):

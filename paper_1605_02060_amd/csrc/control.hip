@@ -71,7 +71,8 @@ __device__ double block1024_min(const double* p, int count, double* red) {
   return block1024_min_of(v, red);
 }
 
-constexpr int kDecideBatch = 16;  // partials in flight per thread in k_decide's pass
+constexpr int kDecideBatch = 16;  // partials of each array in flight per thread in k_decide's pass
+constexpr int kDecideData = 4;    // data partials loaded ahead per thread (kPartMax / 1024)
 
 // Reduce the energy of the evaluated velocity and take the guard decision.
 //  init = 1 : first evaluation of a level (row 0), no decision.
@@ -99,59 +100,63 @@ __device__ __forceinline__ void decide_body(State* st, const double* partR, int 
     }
     return;
   }
-  // one strided pass over the partials of every time step, then one reduction tree
-  // per quantity (the order is fixed, so repeated calls give the same bits).  The
-  // pass loads kDecideBatch partials before it adds them (in the same order), so
+  // One strided pass over the partials of every time step (the regulariser's,
+  // and with a decision the min-det ones), then one reduction tree per quantity;
+  // each thread adds its partials in increasing index order and the trees are
+  // fixed, so repeated calls give the same bits.  Every round loads
+  // kDecideBatch partials of each array before it uses them, and the data
+  // partials (at most kDecideData per thread) come before the first round, so
   // their latencies overlap instead of adding up.
-  double R, D, I;
+  const bool want_det = !init && mode == MODE_GRAD;
+  const int step = blockDim.x;
+  double d = 0.0, im = 0.0;
   {
-    double r = 0.0, d = 0.0, im = 0.0;
-    const int n = T * nfw, step = blockDim.x;
-    int i = threadIdx.x;
-    for (; i + (kDecideBatch - 1) * step < n; i += kDecideBatch * step) {
-      double v[kDecideBatch];
+    double vd[kDecideData], vi[kDecideData];
 #pragma unroll
-      for (int u = 0; u < kDecideBatch; ++u) {
-        const int ii = i + u * step, j = ii / nfw;
-        v[u] = partR[(long long)j * kPartMax + (ii - j * nfw)];
+    for (int u = 0; u < kDecideData; ++u) {
+      const int ii = (int)threadIdx.x + u * step;
+      vd[u] = ii < nfw ? partD[ii] : 0.0;
+      vi[u] = ii < nfw ? partI[ii] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kDecideData; ++u) {
+      if ((int)threadIdx.x + u * step < nfw) {
+        d += vd[u];
+        im += vi[u];
       }
-#pragma unroll
-      for (int u = 0; u < kDecideBatch; ++u) r += v[u];
     }
-    for (; i < n; i += step) {
-      const int j = i / nfw;
-      r += partR[(long long)j * kPartMax + (i - j * nfw)];
+    for (int ii = (int)threadIdx.x + kDecideData * step; ii < nfw; ii += step) {
+      d += partD[ii];
+      im += partI[ii];
     }
-    for (int i = threadIdx.x; i < nfw; i += blockDim.x) {
-      d += partD[i];
-      im += partI[i];
-    }
-    block1024_sum3(r, d, im, red);
-    R = r;
-    D = d;
-    I = im;
   }
-  double md = 0.0;
-  if (!init && mode == MODE_GRAD) {
-    double m = 1e300;
-    const int n = T * nbw, step = blockDim.x;
-    int i = threadIdx.x;
-    for (; i + (kDecideBatch - 1) * step < n; i += kDecideBatch * step) {
-      double v[kDecideBatch];
+  double r = 0.0, m = 1e300;
+  const int nR = T * nfw, nDet = want_det ? T * nbw : 0, nmax = nR > nDet ? nR : nDet;
+  for (int i0 = (int)threadIdx.x; i0 < nmax; i0 += kDecideBatch * step) {
+    double vr[kDecideBatch], vt[kDecideBatch];
 #pragma unroll
-      for (int u = 0; u < kDecideBatch; ++u) {
-        const int ii = i + u * step, j = ii / nbw;
-        v[u] = partDet[(long long)j * kPartMax + (ii - j * nbw)];
+    for (int u = 0; u < kDecideBatch; ++u) {
+      const int ii = i0 + u * step;
+      vr[u] = 0.0;
+      vt[u] = 1e300;
+      if (ii < nR) {
+        const int j = ii / nfw;
+        vr[u] = partR[(long long)j * kPartMax + (ii - j * nfw)];
       }
+      if (ii < nDet) {
+        const int j = ii / nbw;
+        vt[u] = partDet[(long long)j * kPartMax + (ii - j * nbw)];
+      }
+    }
 #pragma unroll
-      for (int u = 0; u < kDecideBatch; ++u) m = fmin(m, v[u]);
+    for (int u = 0; u < kDecideBatch; ++u) {
+      if (i0 + u * step < nR) r += vr[u];
+      m = fmin(m, vt[u]);
     }
-    for (; i < n; i += step) {
-      const int j = i / nbw;
-      m = fmin(m, partDet[(long long)j * kPartMax + (i - j * nbw)]);
-    }
-    md = block1024_min_of(m, red);
   }
+  block1024_sum3(r, d, im, red);
+  const double R = r, D = d, I = im;
+  const double md = want_det ? block1024_min_of(m, red) : 0.0;
   if (threadIdx.x != 0) return;
   const double nan = __longlong_as_double(0x7ff8000000000000LL);
   const double Rt = dt * h3 * R;
